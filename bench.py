@@ -1,0 +1,313 @@
+"""Throughput benchmark of the spherical-harmonic transform on one MI355X.
+
+One step = one round trip (synthesis then analysis) of every field of the
+workload, inputs resident in HBM.  Default workload: TCo1279 octahedral
+reduced Gaussian grid (2560 rings, 20 + 4i points on ring i from each pole,
+6,599,680 points), triangular truncation 1279, 411 fields (3 fields x 137
+levels), Legendre products and FFTs in FP32.  Spectral coefficients are the
+seeded synthetic recipe of paper_1908_06096_amd.inputs (complex N(0,1) scaled
+by 1/(n+1), one generator per field).
+
+Prints one JSON line (metric, value = field-transforms/s, per-stage timings,
+the roofline of the dominant kernel measured with HIP events on the stream the
+kernels run on, and the FP64 CPU oracle's rate on a bounded sample).
+
+    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+PEAK = {  # MI355X published dense peaks
+    "fp64": 78.6e12,
+    "fp32": 157.3e12,
+    "bf16": 2516.6e12,
+    "hbm": 8.0e12,
+}
+
+WORKLOADS = {
+    # name: (truncation, grid, fields)
+    "TCo1279-O1280-F411": (1279, "octahedral", 411),
+    "T399-full-400x800-F411": (399, "full", 411),
+    "T79-full-80x160-F1": (79, "full", 1),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def geometry_counts(N, grid):
+    """Ring lengths, per-ring truncation and the per-m ring counts L_m
+    (north rings carrying m), from the grid definition alone."""
+    if grid == "full":
+        nlat = N + 1
+        nlon = np.full(nlat, 2 * N + 2)
+    else:
+        nlat = 2 * (N + 1)
+        half = 20 + 4 * np.arange(N + 1)
+        nlon = np.concatenate([half, half[::-1]])
+    mmax = np.minimum(N, (nlon - 1) // 2)
+    nh = nlat // 2
+    L = np.array([int(np.sum(mmax[:nh] >= m)) for m in range(N + 1)])
+    return {"nlat": nlat, "npts": int(nlon.sum()), "nfour": int((mmax + 1).sum()), "L": L,
+            "nspec": (N + 1) * (N + 2) // 2}
+
+
+def legendre_flops(N, geo, F):
+    """Algorithmic flops of one Legendre product (either direction):
+    2 flops per multiply-add, 2F real columns, L_m rings by N - m + 1
+    degrees per m (both parity halves, no padding)."""
+    m = np.arange(N + 1)
+    return float(4.0 * F * np.sum(geo["L"] * (N - m + 1)))
+
+
+def stage_bytes(N, geo, F, elem, tab_elem):
+    """Algorithmic HBM bytes per launch of each stage (each operand read or
+    written once)."""
+    m = np.arange(N + 1)
+    tab = float(np.sum(geo["L"] * (N - m + 1))) * tab_elem
+    spec = float(F) * geo["nspec"] * 2 * elem
+    four = float(F) * geo["nfour"] * 2 * elem
+    grid = float(F) * geo["npts"] * elem
+    return {
+        "legendre_inverse": tab + spec + four,
+        "fourier_synthesis": four + grid,
+        "fourier_analysis": grid + four,
+        "legendre_direct": tab + four + spec,
+    }
+
+
+def run_gpu(workload, precision, steps, warmup, seed=0):
+    import torch
+
+    from paper_1908_06096_amd import sht
+    from paper_1908_06096_amd.inputs import spectral_coefficients
+
+    N, grid, F = WORKLOADS[workload]
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    plan = sht.Plan(N, grid, F, precision)
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    log(f"[bench] plan {workload} {precision}: {plan_s:.2f} s, tables {plan.info.table_bytes / 1e9:.2f} GB")
+    dt = np.float64 if precision == "fp64" else np.float32
+    t0 = time.time()
+    s = spectral_coefficients(N, F, seed=seed, dtype=dt)
+    spec = torch.from_numpy(s).cuda()
+    del s
+    grid_t = plan.empty_grid()
+    back = plan.empty_spec()
+    ws = plan.empty_workspace()
+    torch.cuda.synchronize()
+    log(f"[bench] inputs resident ({time.time() - t0:.1f} s)")
+
+    stream = torch.cuda.current_stream()
+    names = ["legendre_inverse", "fourier_synthesis", "fourier_analysis", "legendre_direct"]
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        plan.legendre_inverse(spec, ws)
+        if evs is not None:
+            evs[1].record(stream)
+        plan.fourier_synthesis(ws, grid_t)
+        if evs is not None:
+            evs[2].record(stream)
+        plan.fourier_analysis(grid_t, ws)
+        if evs is not None:
+            evs[3].record(stream)
+        plan.legendre_direct(ws, back)
+        if evs is not None:
+            evs[4].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    log("[bench] warmup done")
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.time()
+    start.record(stream)
+    for k in range(steps):
+        step(events[k])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.time() - wall0
+    total_ms = start.elapsed_time(stop)
+    per_stage = {n: float(np.mean([events[k][i].elapsed_time(events[k][i + 1]) for k in range(steps)]))
+                 for i, n in enumerate(names)}
+    log(f"[bench] timed {steps} steps: {total_ms:.2f} ms (wall {wall * 1e3:.1f} ms); stages {per_stage}")
+
+    # self-consistency: the round trip returns the band-limited input
+    a = spec.double()
+    a[:, : N + 1, 1] = 0
+    rt = float(torch.linalg.vector_norm(back.double() - a) / torch.linalg.vector_norm(a))
+    out = {
+        "plan": plan,
+        "N": N, "grid": grid, "F": F,
+        "total_ms": total_ms, "steps": steps, "per_stage_ms": per_stage,
+        "round_trip_rel_l2": rt, "plan_s": plan_s,
+        "spec": spec, "grid_t": grid_t,
+    }
+    return out
+
+
+def oracle_sample_error(res, precision, seed=0, nrings=4):
+    """Relative L2 of the GPU synthesis against the FP64 oracle on a few
+    rings of field 0 (the oracle evaluates only those rings)."""
+    import oracle
+    from paper_1908_06096_amd.inputs import spectral_coefficients
+
+    N, grid = res["N"], res["grid"]
+    dt = np.float64 if precision == "fp64" else np.float32
+    s = spectral_coefficients(N, 1, seed=seed, dtype=dt)
+    spec_c = s[..., 0].astype(np.float64) + 1j * s[..., 1].astype(np.float64)
+    geo = oracle.grid_geometry(N, grid)
+    rings = np.linspace(0, geo["nlat"] - 1, nrings).astype(int)
+    _f, gref = oracle.inverse(spec_c, N, grid, rings=rings)
+    g0 = res["grid_t"][0].double().cpu().numpy()
+    num = den = 0.0
+    for j in rings:
+        got = g0[geo["off"][j]:geo["off"][j + 1]]
+        num += float(np.sum((got - gref[int(j)][0]) ** 2))
+        den += float(np.sum(gref[int(j)][0] ** 2))
+    return (num / den) ** 0.5
+
+
+def cpu_baseline(workload, seed=0):
+    """The FP64 oracle on the host cores on a bounded sample of the workload:
+    one field; synthesis restricted to a ring subset and analysis restricted
+    to a wavenumber subset, each timed at two subset sizes and extended
+    linearly (fixed cost + per-ring / per-wavenumber cost) to the full ring
+    and wavenumber counts."""
+    import oracle
+    from paper_1908_06096_amd.inputs import grid_noise, spectral_coefficients
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    N, grid, _F = WORKLOADS[workload]
+    geo = oracle.grid_geometry(N, grid)
+    gauss = oracle.gauss_newton(geo["nlat"])
+    s = spectral_coefficients(N, 1, seed=seed)
+    spec_c = s[..., 0] + 1j * s[..., 1]
+    g = grid_noise(geo["npts"], 1, seed=seed)
+
+    def t_inverse(k):
+        rings = np.linspace(0, geo["nlat"] - 1, k).astype(int)
+        t0 = time.perf_counter()
+        oracle.inverse(spec_c, N, grid, rings=rings, geometry=geo, gauss=gauss)
+        return time.perf_counter() - t0
+
+    def t_direct(k):
+        ms = np.linspace(0, N, k).astype(int)
+        t0 = time.perf_counter()
+        oracle.direct(g, N, grid, ms=ms, geometry=geo, gauss=gauss)
+        return time.perf_counter() - t0
+
+    k1, k2 = (8, 16) if N > 500 else (4, 8)
+    i1, i2 = t_inverse(k1), t_inverse(k2)
+    d1, d2 = t_direct(k1), t_direct(k2)
+    bi = max((i2 - i1) / (k2 - k1), 0.0)
+    bd = max((d2 - d1) / (k2 - k1), 0.0)
+    inv_full = max(i1 - k1 * bi, 0.0) + geo["nlat"] * bi
+    dir_full = max(d1 - k1 * bd, 0.0) + (N + 1) * bd
+    value = 2.0 / (inv_full + dir_full)
+    return {
+        "value": value,
+        "unit": "field-transforms/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"{workload}, 1 field: FP64 oracle synthesis on {k1} and {k2} evenly spaced rings and analysis "
+                   f"on {k1} and {k2} evenly spaced wavenumbers ({i1 + i2 + d1 + d2:.1f} s measured), extended "
+                   f"linearly to {geo['nlat']} rings ({inv_full:.1f} s) and {N + 1} wavenumbers ({dir_full:.1f} s)"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="TCo1279-O1280-F411", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-oracle-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the transform is built and measured on a single MI355X "
+              "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    res = run_gpu(args.workload, args.precision, args.steps, args.warmup)
+    N, F = res["N"], res["F"]
+    geo = geometry_counts(N, res["grid"])
+    elem = 8 if args.precision == "fp64" else 4
+    flops = legendre_flops(N, geo, F)
+    nbytes = stage_bytes(N, geo, F, elem, elem)
+    st = res["per_stage_ms"]
+    stages = {}
+    for name, ms in st.items():
+        if name.startswith("legendre"):
+            ach = flops / (ms * 1e-3)
+            stages[name] = {"ms": ms, "bound": "mfma", "achieved_tflops": ach / 1e12,
+                            "frac": ach / PEAK[args.precision], "hbm_gbs": nbytes[name] / (ms * 1e-3) / 1e9}
+        else:
+            ach = nbytes[name] / (ms * 1e-3)
+            stages[name] = {"ms": ms, "bound": "hbm", "achieved_gbs": ach / 1e9, "frac": ach / PEAK["hbm"]}
+    dom = max(st, key=st.get)
+    d = stages[dom]
+    if d["bound"] == "mfma":
+        roof = {"kernel": dom, "bound": "mfma", "achieved": d["achieved_tflops"], "peak": PEAK[args.precision] / 1e12,
+                "unit": "TFLOP/s", "frac": d["frac"], "traffic": None}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": d["achieved_gbs"], "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": d["frac"], "traffic": None}
+
+    ms_per_step = res["total_ms"] / args.steps
+    value = 2.0 * F * args.steps / (res["total_ms"] * 1e-3)
+    out = {
+        "metric": "field-transforms/s",
+        "value": value,
+        "unit": "field-transforms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "truncation": N, "grid": res["grid"], "fields": F,
+                   "precision": args.precision, "step": "inverse + direct of all fields"},
+        "roofline": roof,
+        "stages": stages,
+        "round_trip_rel_l2": res["round_trip_rel_l2"],
+    }
+    if not args.no_oracle_check:
+        out["oracle_rel_l2_sample"] = oracle_sample_error(res, args.precision)
+        log(f"[bench] oracle sample error {out['oracle_rel_l2_sample']:.2e}")
+    res["plan"].close()
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(args.workload)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * sht.h -- C ABI of an MI355X (gfx950) spherical-harmonic transform library.
+ *
+ * The transform is the one the ESCAPE D3.3 spectral-transform dwarf is built
+ * on (report section 4.4.1, defining equation repeated in 4.4.2): a field on a
+ * Gaussian grid is a Fourier series in longitude whose coefficient for zonal
+ * wavenumber m is a Legendre sum over total wavenumber n of the spectral
+ * coefficients a_n^m times the normalised associated Legendre functions
+ * Pbar_n^m(mu), mu = cos(colatitude).  Section 4.2 describes the same
+ * transform as two stages per direction -- per-latitude FFTs in longitude
+ * and one Legendre matrix product per m -- with all latitudes, wavenumbers
+ * and fields exposed to the GPU at once (4.2.2-4.2.3), arrays allocated
+ * once outside the time loop (4.2.3) and no device synchronisation between
+ * calls (4.2.5).  This library keeps that structure.
+ *
+ * Directions:
+ *   inverse  (synthesis)  spectral -> grid
+ *   direct   (analysis)   grid -> spectral
+ *
+ * Conventions (the report leaves these unstated; this library fixes them):
+ *   - integral over mu in [-1, 1] of Pbar_n^m squared is 1; no
+ *     Condon-Shortley phase;
+ *   - real fields: only m >= 0 is stored; Im a_n^0 is ignored on input and
+ *     written as exactly 0 on output;
+ *   - triangular truncation: 0 <= m <= n <= N;
+ *   - Gaussian latitudes are the roots of P_nlat, ordered north to south;
+ *     point k of a ring of n points is at longitude 2 pi k / n;
+ *   - per-ring Fourier truncation mmax_j = min(N, floor((nlon_j - 1) / 2));
+ *   - analysis is Gaussian quadrature: a_n^m = sum_j w_j chat_{j,m}
+ *     Pbar_n^m(mu_j) with chat_{j,m} = (1/nlon_j) sum_k g_{j,k} e^{-i m lam_k}.
+ *
+ * Grids:
+ *   SHT_GRID_FULL        nlat = N + 1 rings of 2N + 2 points (N must be odd,
+ *                        so that every ring has a mirror ring)
+ *   SHT_GRID_OCTAHEDRAL  O(N + 1): nlat = 2(N + 1) rings; ring i counted
+ *                        from either pole has 20 + 4i points
+ *
+ * Precisions:
+ *   SHT_FP64    data, tables, FFT and Legendre products in float64
+ *               (FP64 MFMA)
+ *   SHT_FP32    data, tables, FFT in float32; Legendre products on FP32 MFMA
+ *   SHT_BF16X3  data and FFT in float32; Legendre products with both
+ *               operands split x = hi + lo (bfloat16, round to nearest even)
+ *               and three BF16 MFMA products hi*hi + hi*lo + lo*hi
+ *               accumulated in float32
+ *   Latitudes, weights and Pbar are always computed in float64 on the GPU
+ *   at plan time and rounded once to the table type.
+ *
+ * Layouts (all arrays are device memory owned by the caller unless stated):
+ *   spectral  [F][nspec] complex, real and imaginary parts interleaved,
+ *             nspec = (N+1)(N+2)/2, m-major triangular:
+ *             index(m, n) = m (2N + 3 - m) / 2 + (n - m).
+ *   grid      [F][npts] real, rings north to south, ring j at ring_offset[j].
+ *   element type is double for SHT_FP64, float otherwise.
+ *
+ *   Fourier workspace, synthesis form (written by sht_legendre_inverse,
+ *   read by sht_fourier_synthesis): for ring j (0..nlat-1), wavenumber
+ *   m (0..mmax_j) and field f, the complex coefficient c_{j,m} of field f
+ *   is at complex index (four_row[j] + m) * fpad + f, with
+ *   four_row[j] = sum_{i<j} (mmax_i + 1) and fpad = F rounded up to 16.
+ *
+ *   Fourier workspace, analysis form (written by sht_fourier_analysis,
+ *   read by sht_legendre_direct): for north ring j (0..nlat/2-1), m and
+ *   parity p (0: symmetric S, 1: antisymmetric A) the complex value is at
+ *   ((four_row[j] + m) * 2 + p) * fpad + f, where
+ *   S = (w_j/nlon_j) (chat(ring j) + chat(mirror ring)) and
+ *   A = (w_j/nlon_j) (chat(ring j) - chat(mirror ring)).
+ *
+ * Ownership and concurrency: a plan owns its device tables and metadata and
+ * is immutable after creation.  sht_inverse / sht_direct and the stage calls
+ * never allocate and never synchronise the host; they enqueue on the given
+ * HIP stream (NULL = the default stream) and return.  Concurrent calls on
+ * one plan are safe if each has its own workspace and outputs.
+ *
+ * Errors: every call returns SHT_OK (0) or a negative code; nothing throws
+ * across the ABI.  After SHT_EHIP, sht_last_hip_error() returns the HIP
+ * error code of the failing call (per thread).
+ */
+#ifndef SHT_H
+#define SHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum sht_grid { SHT_GRID_FULL = 0, SHT_GRID_OCTAHEDRAL = 1 };
+enum sht_prec { SHT_FP64 = 0, SHT_FP32 = 1, SHT_BF16X3 = 2 };
+
+enum sht_status {
+  SHT_OK = 0,
+  SHT_EINVAL = -1,       /* bad argument (null pointer, out-of-range value) */
+  SHT_EUNSUPPORTED = -2, /* (truncation, grid, precision) not supported     */
+  SHT_ENOMEM = -3,       /* device allocation failed at plan creation       */
+  SHT_EHIP = -4          /* a HIP call failed; see sht_last_hip_error()     */
+};
+
+typedef struct sht_plan_s* sht_plan_t;
+
+typedef struct sht_info {
+  int32_t truncation; /* N */
+  int32_t grid;       /* enum sht_grid */
+  int32_t nfields;    /* F */
+  int32_t precision;  /* enum sht_prec */
+  int32_t nlat;       /* number of rings */
+  int32_t fpad;       /* F rounded up to 16: field stride of the workspace */
+  int64_t npts;       /* grid points per field */
+  int64_t nspec;      /* spectral coefficients per field */
+  int64_t nfour;      /* sum over rings of (mmax_j + 1) */
+  int64_t workspace_bytes;
+  int64_t table_bytes;   /* resident Pbar tables */
+  int64_t plan_bytes;    /* every device byte the plan holds */
+  int32_t elem_bytes;    /* 8 for SHT_FP64, 4 otherwise */
+  int32_t reserved;
+} sht_info;
+
+/* Create a plan: geometry, Gaussian latitudes and weights (Newton iteration
+ * on P_nlat in float64), Pbar_n^m tables (float64 recurrence, rounded once
+ * to the table type), FFT twiddle and chirp tables, and the Legendre work
+ * lists.  Every table is computed by kernels on `hip_stream`; the call
+ * synchronises that stream once before returning.  `truncation` >= 1 (odd
+ * for SHT_GRID_FULL), `nfields` >= 1.  On success *out receives the plan. */
+int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields,
+                    int precision, void* hip_stream);
+
+/* Release a plan and its device memory (synchronises the device first). */
+int sht_plan_destroy(sht_plan_t plan);
+
+/* Sizes of a plan (host struct, no device work). */
+int sht_plan_info(sht_plan_t plan, sht_info* out);
+
+/* Copy the plan's geometry to host arrays of nlat entries each (any may be
+ * NULL): latitudes mu, Gaussian weights w, ring lengths nlon, per-ring
+ * Fourier truncation mmax, and four_row (nlat + 1 entries: row offsets of
+ * the Fourier workspace).  ring_offset receives nlat + 1 grid offsets.
+ * Synchronous. */
+int sht_plan_geometry(sht_plan_t plan, double* mu, double* w, int32_t* nlon,
+                      int32_t* mmax, int64_t* ring_offset, int64_t* four_row);
+
+/* Copy the resident Pbar table of wavenumber m to host as float64,
+ * [rows][N - m + 1] with rows = the north rings that carry m (mmax_j >= m),
+ * pole to equator; *first_ring receives the index of the first such ring.
+ * For SHT_BF16X3 the value is hi + lo.  `out` must hold rows * (N-m+1)
+ * doubles where rows = nlat/2 - *first_ring; pass out = NULL to query
+ * first_ring only.  Synchronous.  For tests of the plan kernels. */
+int sht_plan_legendre_table(sht_plan_t plan, int m, double* out, int32_t* first_ring);
+
+/* Bytes of workspace sht_inverse / sht_direct need (the Fourier buffer). */
+size_t sht_workspace_size(sht_plan_t plan);
+
+/* Synthesis of all F fields: spectral -> grid.  `spec` [F][nspec] complex,
+ * `grid` [F][npts] real, `workspace` >= sht_workspace_size bytes, all device
+ * pointers aligned to 16 bytes.  Enqueues sht_legendre_inverse then
+ * sht_fourier_synthesis on the stream.  Asynchronous. */
+int sht_inverse(sht_plan_t plan, const void* spec, void* grid, void* workspace,
+                void* hip_stream);
+
+/* Analysis of all F fields: grid -> spectral.  Enqueues
+ * sht_fourier_analysis then sht_legendre_direct.  Asynchronous. */
+int sht_direct(sht_plan_t plan, const void* grid, void* spec, void* workspace,
+               void* hip_stream);
+
+/* Stage 1 of synthesis: per m, S_m = Pbar_even a_even and A_m = Pbar_odd
+ * a_odd over the north rings carrying m, then c(ring j) = S + A and
+ * c(mirror ring) = S - A, written in the synthesis form of the Fourier
+ * workspace (report 4.2.4: the Legendre transform as matrix products). */
+int sht_legendre_inverse(sht_plan_t plan, const void* spec, void* fourier,
+                         void* hip_stream);
+
+/* Stage 2 of synthesis: per ring, the real inverse DFT of c_{j,0..mmax_j}
+ * (zero above mmax_j) onto the ring's nlon_j points (report 4.2.5). */
+int sht_fourier_synthesis(sht_plan_t plan, const void* fourier, void* grid,
+                          void* hip_stream);
+
+/* Stage 1 of analysis: per ring pair, the real DFT, the (w_j / nlon_j)
+ * scaling and the symmetric/antisymmetric fold, written in the analysis
+ * form of the Fourier workspace. */
+int sht_fourier_analysis(sht_plan_t plan, const void* grid, void* fourier,
+                         void* hip_stream);
+
+/* Stage 2 of analysis: per m, a_n^m = Pbar^T S (n - m even) or Pbar^T A
+ * (n - m odd) summed over the north rings carrying m. */
+int sht_legendre_direct(sht_plan_t plan, const void* fourier, void* spec,
+                        void* hip_stream);
+
+/* Human-readable text of a status code. */
+const char* sht_strerror(int status);
+
+/* HIP error code of the last SHT_EHIP on this thread (0 if none). */
+int sht_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHT_H */

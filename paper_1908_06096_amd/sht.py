@@ -1,0 +1,280 @@
+"""Python binding of the C-ABI library ``libshtmi.so`` (include/sht.h).
+
+Argument marshalling only: every step of the transform runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current HIP stream.
+The library must have been built (``python -m paper_1908_06096_amd.build``);
+loading raises if it is missing -- there is no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["Plan", "SHTError", "library", "LIB_PATH", "GRIDS", "PRECISIONS", "exported_symbols"]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libshtmi.so")
+GRIDS = {"full": 0, "octahedral": 1}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+_c_int_p = ctypes.POINTER(ctypes.c_int32)
+_c_i64_p = ctypes.POINTER(ctypes.c_int64)
+_c_dbl_p = ctypes.POINTER(ctypes.c_double)
+
+
+class SHTInfo(ctypes.Structure):
+    _fields_ = [
+        ("truncation", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("nfields", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("nlat", ctypes.c_int32),
+        ("fpad", ctypes.c_int32),
+        ("npts", ctypes.c_int64),
+        ("nspec", ctypes.c_int64),
+        ("nfour", ctypes.c_int64),
+        ("workspace_bytes", ctypes.c_int64),
+        ("table_bytes", ctypes.c_int64),
+        ("plan_bytes", ctypes.c_int64),
+        ("elem_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+_SIGNATURES = {
+    "sht_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_void_p]),
+    "sht_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sht_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SHTInfo)]),
+    "sht_plan_geometry": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_int_p, _c_int_p, _c_i64_p,
+                                         _c_i64_p]),
+    "sht_plan_legendre_table": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _c_dbl_p, _c_int_p]),
+    "sht_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "sht_inverse": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "sht_direct": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "sht_legendre_inverse": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
+    "sht_fourier_synthesis": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
+    "sht_fourier_analysis": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
+    "sht_legendre_direct": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
+    "sht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "sht_last_hip_error": (ctypes.c_int, []),
+}
+
+_LIB = None
+
+
+def library():
+    """Load libshtmi.so (once) and declare its signatures."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1908_06096_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def exported_symbols():
+    """Names the binding declares (all of them are in include/sht.h)."""
+    return sorted(_SIGNATURES)
+
+
+class SHTError(RuntimeError):
+    def __init__(self, status, call):
+        lib = library()
+        msg = lib.sht_strerror(status).decode()
+        hip = lib.sht_last_hip_error() if status == -4 else 0
+        super().__init__(f"{call}: {msg} (status {status}{', hip error %d' % hip if hip else ''})")
+        self.status = status
+
+
+def _check(status, call):
+    if status != 0:
+        raise SHTError(status, call)
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A transform plan: truncation N, grid ('full' | 'octahedral'), F fields,
+    precision ('fp64' | 'fp32' | 'bf16x3').  Tables are computed on the GPU at
+    creation and stay resident until ``close()``."""
+
+    def __init__(self, truncation, grid="full", nfields=1, precision="fp64", stream=None):
+        lib = library()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        _check(lib.sht_plan_create(ctypes.byref(self._h), int(truncation), GRIDS[grid], int(nfields),
+                                   PRECISIONS[precision], _stream_handle(stream)), "sht_plan_create")
+        info = SHTInfo()
+        _check(lib.sht_plan_info(self._h, ctypes.byref(info)), "sht_plan_info")
+        self.info = info
+        self.truncation = int(truncation)
+        self.grid = grid
+        self.nfields = int(nfields)
+        self.precision = precision
+        self.nlat = info.nlat
+        self.npts = info.npts
+        self.nspec = info.nspec
+        self.nfour = info.nfour
+        self.fpad = info.fpad
+
+    # ---- lifetime ----
+    def close(self):
+        if self._h:
+            _check(self._lib.sht_plan_destroy(self._h), "sht_plan_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- metadata ----
+    @property
+    def dtype(self):
+        import torch
+
+        return torch.float64 if self.precision == "fp64" else torch.float32
+
+    @property
+    def workspace_bytes(self):
+        return int(self._lib.sht_workspace_size(self._h))
+
+    def geometry(self):
+        n = self.nlat
+        mu = np.zeros(n)
+        w = np.zeros(n)
+        nlon = np.zeros(n, dtype=np.int32)
+        mmax = np.zeros(n, dtype=np.int32)
+        off = np.zeros(n + 1, dtype=np.int64)
+        frow = np.zeros(n + 1, dtype=np.int64)
+        _check(self._lib.sht_plan_geometry(self._h, mu.ctypes.data_as(_c_dbl_p), w.ctypes.data_as(_c_dbl_p),
+                                           nlon.ctypes.data_as(_c_int_p), mmax.ctypes.data_as(_c_int_p),
+                                           off.ctypes.data_as(_c_i64_p), frow.ctypes.data_as(_c_i64_p)),
+               "sht_plan_geometry")
+        return {"mu": mu, "w": w, "nlon": nlon, "mmax": mmax, "ring_offset": off, "four_row": frow}
+
+    def legendre_table(self, m):
+        first = ctypes.c_int32()
+        _check(self._lib.sht_plan_legendre_table(self._h, int(m), None, ctypes.byref(first)),
+               "sht_plan_legendre_table")
+        rows = self.nlat // 2 - first.value
+        out = np.zeros((rows, self.truncation - m + 1))
+        if out.size:
+            _check(self._lib.sht_plan_legendre_table(self._h, int(m), out.ctypes.data_as(_c_dbl_p),
+                                                     ctypes.byref(first)), "sht_plan_legendre_table")
+        return first.value, out
+
+    # ---- buffers ----
+    def empty_spec(self, device="cuda"):
+        import torch
+
+        return torch.empty((self.nfields, self.nspec, 2), dtype=self.dtype, device=device)
+
+    def empty_grid(self, device="cuda"):
+        import torch
+
+        return torch.empty((self.nfields, self.npts), dtype=self.dtype, device=device)
+
+    def empty_workspace(self, device="cuda"):
+        import torch
+
+        return torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+
+    def _ptr(self, t, numel, name, dtype=None):
+        import torch
+
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        want = self.dtype if dtype is None else dtype
+        if t.dtype != want:
+            raise TypeError(f"{name} must be {want}, got {t.dtype}")
+        if t.numel() < numel:
+            raise ValueError(f"{name} too small: {t.numel()} < {numel}")
+        if t.data_ptr() % 16:
+            raise ValueError(f"{name} must be 16-byte aligned")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _spec(self, t):
+        return self._ptr(t, self.nfields * self.nspec * 2, "spec")
+
+    def _grid(self, t):
+        return self._ptr(t, self.nfields * self.npts, "grid")
+
+    def _ws(self, t):
+        import torch
+
+        return self._ptr(t, self.workspace_bytes, "workspace", dtype=torch.uint8)
+
+    # ---- transforms ----
+    def inverse(self, spec, grid=None, workspace=None, stream=None):
+        """Synthesis spectral -> grid, enqueued on the current stream."""
+        grid = self.empty_grid(spec.device) if grid is None else grid
+        workspace = self.empty_workspace(spec.device) if workspace is None else workspace
+        _check(self._lib.sht_inverse(self._h, self._spec(spec), self._grid(grid), self._ws(workspace),
+                                     _stream_handle(stream)), "sht_inverse")
+        return grid
+
+    def direct(self, grid, spec=None, workspace=None, stream=None):
+        """Analysis grid -> spectral, enqueued on the current stream."""
+        spec = self.empty_spec(grid.device) if spec is None else spec
+        workspace = self.empty_workspace(grid.device) if workspace is None else workspace
+        _check(self._lib.sht_direct(self._h, self._grid(grid), self._spec(spec), self._ws(workspace),
+                                    _stream_handle(stream)), "sht_direct")
+        return spec
+
+    def legendre_inverse(self, spec, workspace, stream=None):
+        _check(self._lib.sht_legendre_inverse(self._h, self._spec(spec), self._ws(workspace),
+                                              _stream_handle(stream)), "sht_legendre_inverse")
+        return workspace
+
+    def fourier_synthesis(self, workspace, grid, stream=None):
+        _check(self._lib.sht_fourier_synthesis(self._h, self._ws(workspace), self._grid(grid),
+                                               _stream_handle(stream)), "sht_fourier_synthesis")
+        return grid
+
+    def fourier_analysis(self, grid, workspace, stream=None):
+        _check(self._lib.sht_fourier_analysis(self._h, self._grid(grid), self._ws(workspace),
+                                              _stream_handle(stream)), "sht_fourier_analysis")
+        return workspace
+
+    def legendre_direct(self, workspace, spec, stream=None):
+        _check(self._lib.sht_legendre_direct(self._h, self._ws(workspace), self._spec(spec),
+                                             _stream_handle(stream)), "sht_legendre_direct")
+        return spec
+
+    # ---- workspace views (documented layouts of include/sht.h) ----
+    def synthesis_fourier_view(self, workspace):
+        """Complex view [nfour, fpad] of the synthesis-form workspace."""
+        import torch
+
+        t = workspace[: self.nfour * self.fpad * 2 * self.info.elem_bytes].view(self.dtype)
+        return torch.view_as_complex(t.view(self.nfour, self.fpad, 2))
+
+    def analysis_fourier_view(self, workspace):
+        """Complex view [nfour/2, 2 (S, A), fpad] of the analysis-form workspace
+        (row index four_row[j] + m for north ring j)."""
+        import torch
+
+        t = workspace[: self.nfour * self.fpad * 2 * self.info.elem_bytes].view(self.dtype)
+        return torch.view_as_complex(t.view(self.nfour // 2, 2, self.fpad, 2))

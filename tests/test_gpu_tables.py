@@ -1,0 +1,77 @@
+"""Plan-time kernels against the oracle: Gaussian latitudes and weights
+(float64 Newton on the GPU), ring geometry, and the resident Pbar tables.
+
+Both sides converge Newton's iteration to within an ulp of each root, but
+not always to the same float.  The tolerances below are the first-order
+effect of a 2-ulp difference in mu, derived from identities that hold at a
+root or for every mu:
+* weight: at a root of P_n, P'' = 2 mu P' / (1 - mu^2), so
+  d ln w / d mu = -2 mu / (1 - mu^2);
+* Pbar: (1 - mu^2) dPbar_n^m/dmu = -n mu Pbar_n^m + c Pbar_{n-1}^m with
+  c = sqrt((2n+1)/(2n-1) (n^2 - m^2)) <= 1.01 n, so
+  |dPbar_n^m/dmu| <= 2.1 n max|Pbar| / (1 - mu^2).
+Near the poles these amplify an ulp of mu by 1/(1 - mu^2)."""
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sht():
+    from paper_1908_06096_amd import sht as mod
+
+    return mod
+
+
+@pytest.mark.parametrize("N,grid", [(1, "full"), (79, "full"), (399, "full"), (31, "octahedral"), (1279, "octahedral")])
+def test_latitudes_weights_geometry(sht, N, grid):
+    with sht.Plan(N, grid, 1, "fp32" if N == 1279 else "fp64") as plan:
+        g = plan.geometry()
+        geo = oracle.grid_geometry(N, grid)
+        mu, w = oracle.gauss_newton(geo["nlat"])
+        dmu = 2 * np.spacing(np.abs(mu)) + 1e-300
+        assert np.all(np.abs(g["mu"] - mu) <= dmu)
+        one_m = (1 - mu) * (1 + mu)
+        bound = dmu * 2 * np.abs(mu) / one_m + 1e-14
+        assert np.all(np.abs(g["w"] - w) / w <= bound)
+        assert abs(g["w"].sum() - 2.0) <= 4e-15 * max(1.0, geo["nlat"] / 80)
+        assert np.array_equal(g["nlon"], geo["nlon"])
+        assert np.array_equal(g["mmax"], geo["mmax"])
+        assert np.array_equal(g["ring_offset"], geo["off"])
+        assert np.array_equal(g["four_row"], geo["foff"])
+        assert plan.npts == geo["npts"] and plan.nfour == geo["nfour"] and plan.nspec == geo["nspec"]
+
+
+def _first_ring(geo, m):
+    nh = geo["nlat"] // 2
+    return int(np.argmax(geo["mmax"][:nh] >= m))
+
+
+@pytest.mark.parametrize("N,grid,prec", [(79, "full", "fp64"), (63, "octahedral", "fp64"), (63, "octahedral", "fp32"),
+                                         (1279, "octahedral", "fp64")])
+def test_pbar_tables(sht, N, grid, prec):
+    with sht.Plan(N, grid, 1, prec) as plan:
+        geo = oracle.grid_geometry(N, grid)
+        mu, _w = oracle.gauss_newton(geo["nlat"])
+        nh = geo["nlat"] // 2
+        ms = sorted(set([0, 1, 2, N // 3, N // 2, N - 1, N]))
+        for m in ms:
+            first, tab = plan.legendre_table(m)
+            assert first == _first_ring(geo, m)
+            ref = oracle.pbar(m, N, mu[first:nh])
+            assert tab.shape == ref.shape
+            x = mu[first:nh]
+            scale = max(1.0, float(np.max(np.abs(ref))))
+            n = np.arange(m, N + 1)[None, :]
+            dmu = 2 * np.spacing(np.abs(x))[:, None]
+            bound64 = 1e-13 * scale + dmu * 2.1 * np.maximum(n, 1) * scale / ((1 - x) * (1 + x))[:, None]
+            if prec == "fp64":
+                assert np.all(np.abs(tab - ref) <= bound64), m
+            else:
+                ulp = np.spacing(np.abs(ref.astype(np.float32))).astype(np.float64)
+                r32 = ref.astype(np.float32).astype(np.float64)
+                assert np.all(np.abs(tab - r32) <= ulp + bound64), m
