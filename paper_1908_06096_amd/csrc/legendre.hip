@@ -46,6 +46,27 @@ __device__ inline int acc_row(int lane, int e) {
   return sizeof(T) == 8 ? 4 * e + (lane >> 4) : 4 * (lane >> 4) + e;
 }
 
+// 16-byte vectors and complex pairs of the element type.
+template <typename T>
+struct Vec;
+template <>
+struct Vec<float> {
+  typedef float4 type;
+  typedef float2 pair;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec<double> {
+  typedef double2 type;
+  typedef double2 pair;
+  static constexpr int n = 2;
+};
+
+// LDS rows are padded by 16 elements: consecutive rows then start 16 banks
+// apart, so the 64 lanes of an MFMA operand read (4 rows x 16 columns) hit
+// distinct banks.
+constexpr int LDS_PAD = 16;
+
 // ---------------------------------------------------------------------------
 // Synthesis: for m and the tile of north-ring rows [t0, t0 + BM) and real
 // columns [c0, c0 + BN):
@@ -53,20 +74,30 @@ __device__ inline int acc_row(int lane, int e) {
 //   c(ring)        = S + A
 //   c(mirror ring) = S - A
 // Four waves in a 2 x 2 arrangement, each owning a (BM/2) x (BN/2) block of
-// both accumulators.  One iteration consumes KCH k of each parity
-// (2 KCH consecutive n).
+// both accumulators.  One iteration consumes KI k of each parity (2 KI
+// consecutive n); the next iteration's operands are fetched into registers
+// while the current one is multiplied out of LDS.
 // ---------------------------------------------------------------------------
 
-template <typename T, int BM, int BN>
-__global__ __launch_bounds__(256) void legendre_inverse_kernel(DevPlan p, const WorkItem* items,
+template <typename T, int BM, int BN, int KI>
+__global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(DevPlan p, const WorkItem* items,
                                                                const T* __restrict__ spec,
                                                                T* __restrict__ four) {
   typedef typename Acc<T>::type acc_t;
+  typedef typename Vec<T>::type V;
+  typedef typename Vec<T>::pair C2;
+  constexpr int VN = Vec<T>::n;
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int IM = WM / 16, IN = WN / 16;
-  constexpr int KI = KCH;
-  __shared__ T As[2][KI][BM];
-  __shared__ T Bs[2][KI][BN];
+  constexpr int NC = KI / KCH;             // table chunks per parity per iteration
+  constexpr int AUNITS = 2 * NC * BM;      // (parity, chunk, row) units of KCH elements
+  constexpr int AU = AUNITS / 256;
+  constexpr int FT = BN / 2;               // fields per tile
+  constexpr int TPF = 256 / FT;            // threads per field
+  constexpr int NB = 2 * KI / TPF;         // complex values per thread per iteration
+  static_assert(AUNITS % 256 == 0 && 256 % FT == 0 && (2 * KI) % TPF == 0 && TPF % 2 == 0, "tile shape");
+  __shared__ T As[2][KI][BM + LDS_PAD];
+  __shared__ T Bs[2][KI][BN + LDS_PAD];
 
   const WorkItem it = items[blockIdx.x];
   const MInfo mi = p.ms[it.m];
@@ -77,59 +108,89 @@ __global__ __launch_bounds__(256) void legendre_inverse_kernel(DevPlan p, const 
   const int wr = wave >> 1, wc = wave & 1;
   const T* tab = (const T*)p.tab;
   const int twoF = 2 * p.F;
-  const int nk = (mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1]) / KI;
+  const int kpmax = mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1];
+  const int nk = (kpmax + KI - 1) / KI;
+
+  // table units owned by this thread
+  int64_t a_base[AU];
+  int a_par[AU], a_ch[AU], a_row[AU], a_nch[AU];
+  bool a_ok[AU];
+#pragma unroll
+  for (int a = 0; a < AU; ++a) {
+    const int u = tid + 256 * a;
+    a_par[a] = u / (NC * BM);
+    a_ch[a] = (u / BM) % NC;
+    a_row[a] = u % BM;
+    const int64_t toff = a_par[a] ? mi.toff[1] : mi.toff[0];
+    a_nch[a] = (a_par[a] ? mi.Kp[1] : mi.Kp[0]) / KCH;
+    a_ok[a] = it.t0 + a_row[a] < mi.Lp;
+    a_base[a] = toff + (int64_t)a_ch[a] * mi.Lp * KCH + (int64_t)(it.t0 + a_row[a]) * KCH;
+  }
+  const int64_t a_step = (int64_t)NC * mi.Lp * KCH;
+  // spectral values owned by this thread: field fi, n offsets q + TPF j
+  const int fi = tid / TPF;
+  const int q = tid % TPF;
+  const int f = it.c0 / 2 + fi;
+  const bool f_ok = f < p.F;
+  const C2* sp = (const C2*)spec + ((int64_t)(f_ok ? f : 0) * p.nspec + mi.spec_off);
+  const int b_par = q & 1;
+
+  V ra[AU][KCH / VN];
+  C2 rb[NB];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int a = 0; a < AU; ++a) {
+      const bool ok = a_ok[a] && (kc * NC + a_ch[a] < a_nch[a]);
+      const V* src = (const V*)(tab + a_base[a] + kc * a_step);
+#pragma unroll
+      for (int v = 0; v < KCH / VN; ++v) ra[a][v] = ok ? src[v] : V{};
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int d = 2 * KI * kc + q + TPF * j;  // n - m
+      C2 x = C2{};
+      if (f_ok && m + d <= p.N) x = sp[d];
+      if (m == 0) x.y = 0;
+      rb[j] = x;
+    }
+  };
 
   acc_t acc[2][IM][IN];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int par = 0; par < 2; ++par)
 #pragma unroll
     for (int i = 0; i < IM; ++i)
 #pragma unroll
-      for (int j = 0; j < IN; ++j) acc[q][i][j] = acc_t{0, 0, 0, 0};
+      for (int j = 0; j < IN; ++j) acc[par][i][j] = acc_t{0, 0, 0, 0};
 
+  fetch(0);
   for (int kc = 0; kc < nk; ++kc) {
-    // table chunk kc of both parities, rows [t0, t0 + BM) -> As[par][kk][r]
-    for (int idx = tid; idx < 2 * BM * KI; idx += 256) {
-      const int par = idx / (BM * KI);
-      const int rem = idx - par * (BM * KI);
-      const int r = rem / KI;
-      const int kk = rem - r * KI;
-      const int row = it.t0 + r;
-      const int64_t toff = par ? mi.toff[1] : mi.toff[0];
-      const int kp = par ? mi.Kp[1] : mi.Kp[0];
-      T v = 0;
-      if (row < mi.Lp && kc * KI < kp) v = tab[toff + (int64_t)kc * mi.Lp * KI + (int64_t)row * KI + kk];
-      As[par][kk][r] = v;
+#pragma unroll
+    for (int a = 0; a < AU; ++a) {
+      const T* e = (const T*)ra[a];
+#pragma unroll
+      for (int kk = 0; kk < KCH; ++kk) As[a_par[a]][a_ch[a] * KCH + kk][a_row[a]] = e[kk];
     }
-    // spectral n = m + 2 KI kc + i (i < 2 KI), fields [c0/2, c0/2 + BN/2) -> Bs[i&1][i>>1][c]
-    for (int idx = tid; idx < (BN / 2) * 2 * KI; idx += 256) {
-      const int fi = idx / (2 * KI);
-      const int i = idx - fi * (2 * KI);
-      const int f = it.c0 / 2 + fi;
-      const int n = m + 2 * KI * kc + i;
-      T re = 0, im = 0;
-      if (n <= p.N && f < p.F) {
-        const int64_t e = ((int64_t)f * p.nspec + mi.spec_off + (n - m)) * 2;
-        re = spec[e];
-        im = (m == 0) ? (T)0 : spec[e + 1];
-      }
-      Bs[i & 1][i >> 1][2 * fi] = re;
-      Bs[i & 1][i >> 1][2 * fi + 1] = im;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int k = (q >> 1) + (TPF / 2) * j;
+      *(C2*)&Bs[b_par][k][2 * fi] = rb[j];
     }
     __syncthreads();
+    if (kc + 1 < nk) fetch(kc + 1);
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
 #pragma unroll
       for (int ks = 0; ks < KI / 4; ++ks) {
-        T a[IM], b[IN];
+        T av[IM], bv[IN];
 #pragma unroll
-        for (int i = 0; i < IM; ++i) a[i] = As[par][ks * 4 + (lane >> 4)][wr * WM + i * 16 + (lane & 15)];
+        for (int i = 0; i < IM; ++i) av[i] = As[par][ks * 4 + (lane >> 4)][wr * WM + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < IN; ++j) b[j] = Bs[par][ks * 4 + (lane >> 4)][wc * WN + j * 16 + (lane & 15)];
+        for (int j = 0; j < IN; ++j) bv[j] = Bs[par][ks * 4 + (lane >> 4)][wc * WN + j * 16 + (lane & 15)];
 #pragma unroll
         for (int i = 0; i < IM; ++i)
 #pragma unroll
-          for (int j = 0; j < IN; ++j) acc[par][i][j] = mfma16x16x4(a[i], b[j], acc[par][i][j]);
+          for (int j = 0; j < IN; ++j) acc[par][i][j] = mfma16x16x4(av[i], bv[j], acc[par][i][j]);
       }
     }
     __syncthreads();
@@ -139,18 +200,20 @@ __global__ __launch_bounds__(256) void legendre_inverse_kernel(DevPlan p, const 
 #pragma unroll
   for (int i = 0; i < IM; ++i) {
 #pragma unroll
-    for (int j = 0; j < IN; ++j) {
-      const int col = it.c0 + wc * WN + j * 16 + (lane & 15);
+    for (int e = 0; e < 4; ++e) {
+      const int row = it.t0 + wr * WM + i * 16 + acc_row<T>(lane, e);
+      if (row >= mi.L) continue;
+      const RingInfo rn = p.rings[mi.first_ring + row];
+      T* dn = four + (rn.frow + m) * rowlen;
+      T* ds = four + (p.rings[rn.mirror].frow + m) * rowlen;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = it.t0 + wr * WM + i * 16 + acc_row<T>(lane, e);
-        if (row < mi.L && col < twoF) {
-          const RingInfo rn = p.rings[mi.first_ring + row];
-          const RingInfo rs = p.rings[rn.mirror];
+      for (int j = 0; j < IN; ++j) {
+        const int col = it.c0 + wc * WN + j * 16 + (lane & 15);
+        if (col < twoF) {
           const T S = acc[0][i][j][e];
           const T A = acc[1][i][j][e];
-          four[(rn.frow + m) * rowlen + col] = S + A;
-          four[(rs.frow + m) * rowlen + col] = S - A;
+          dn[col] = S + A;
+          ds[col] = S - A;
         }
       }
     }
@@ -160,21 +223,31 @@ __global__ __launch_bounds__(256) void legendre_inverse_kernel(DevPlan p, const 
 // ---------------------------------------------------------------------------
 // Analysis: for m, output k tile [t0, t0 + BK) and real columns [c0, c0 + BC):
 //   a[m + 2k + par][c] = sum_r T_par[r][k] X_par[r][c],  X_0 = S, X_1 = A,
-// computed transposed (rows c, columns k) so that each lane holds the real
-// and imaginary part of one coefficient.  The sum runs over the north rings
-// carrying m, KJ rings per iteration.
+// computed transposed (rows c, columns k) so that, in f32, each lane holds
+// the real and imaginary part of one coefficient.  The sum runs over the
+// north rings carrying m, KJ rings per iteration, with the next rings'
+// operands fetched into registers during the multiply.
 // ---------------------------------------------------------------------------
 
-template <typename T, int BC, int BK>
-__global__ __launch_bounds__(256) void legendre_direct_kernel(DevPlan p, const WorkItem* items,
+template <typename T, int BC, int BK, int KJ>
+__global__ __launch_bounds__(256, 2) void legendre_direct_kernel(DevPlan p, const WorkItem* items,
                                                               const T* __restrict__ four,
                                                               T* __restrict__ spec) {
   typedef typename Acc<T>::type acc_t;
+  typedef typename Vec<T>::type V;
+  typedef typename Vec<T>::pair C2;
+  constexpr int VN = Vec<T>::n;
   constexpr int WC = BC / 2, WK = BK / 2;
   constexpr int IC = WC / 16, IK = WK / 16;
-  constexpr int KJ = 16;
-  __shared__ T Xs[2][KJ][BC];
-  __shared__ T Ts[2][KJ][BK];
+  constexpr int CS = BC / VN;                 // vectors per X row segment
+  constexpr int XUNITS = 2 * KJ * CS;
+  constexpr int XU = XUNITS / 256;
+  constexpr int NCH = BK / KCH;               // table chunks per parity
+  constexpr int TUNITS = 2 * NCH * KJ;        // (parity, chunk, ring) units of KCH elements
+  constexpr int TU = TUNITS / 256;
+  static_assert(XUNITS % 256 == 0 && TUNITS % 256 == 0 && KJ % 4 == 0, "tile shape");
+  __shared__ T Xs[2][KJ][BC + LDS_PAD];
+  __shared__ T Ts[2][KJ][BK + LDS_PAD];
 
   const WorkItem it = items[blockIdx.x];
   const MInfo mi = p.ms[it.m];
@@ -186,58 +259,86 @@ __global__ __launch_bounds__(256) void legendre_direct_kernel(DevPlan p, const W
   const T* tab = (const T*)p.tab;
   const int twoF = 2 * p.F;
   const int64_t rowlen = 2 * (int64_t)p.Fp;
+  const int nj = (mi.L + KJ - 1) / KJ;
+
+  int x_par[XU], x_rr[XU], x_c[XU];
+#pragma unroll
+  for (int a = 0; a < XU; ++a) {
+    const int u = tid + 256 * a;
+    x_c[a] = (u % CS) * VN;
+    x_rr[a] = (u / CS) % KJ;
+    x_par[a] = u / (CS * KJ);
+  }
+  const bool x_cok = true;  // every column read stays inside its 2 Fp row
+  int64_t t_base[TU];
+  int t_par[TU], t_ch[TU], t_rr[TU];
+  bool t_ok[TU];
+#pragma unroll
+  for (int a = 0; a < TU; ++a) {
+    const int u = tid + 256 * a;
+    t_rr[a] = u % KJ;
+    t_ch[a] = (u / KJ) % NCH;
+    t_par[a] = u / (KJ * NCH);
+    const int kch = it.t0 / KCH + t_ch[a];
+    const int kp = t_par[a] ? mi.Kp[1] : mi.Kp[0];
+    t_ok[a] = kch * KCH < kp;
+    t_base[a] = (t_par[a] ? mi.toff[1] : mi.toff[0]) + (int64_t)kch * mi.Lp * KCH + (int64_t)t_rr[a] * KCH;
+  }
+
+  V rx[XU];
+  V rt[TU][KCH / VN];
+  auto fetch = [&](int jc) {
+    const int r0 = jc * KJ;
+#pragma unroll
+    for (int a = 0; a < XU; ++a) {
+      const int r = r0 + x_rr[a];
+      V v = V{};
+      const int c = it.c0 + x_c[a];
+      if (r < mi.L && c < 2 * p.Fp && x_cok) {
+        const int64_t fr = p.rings[mi.first_ring + r].frow;
+        v = *(const V*)(four + ((fr + m) * 2 + x_par[a]) * rowlen + c);
+      }
+      rx[a] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < TU; ++a) {
+      const V* src = (const V*)(tab + t_base[a] + (int64_t)r0 * KCH);
+#pragma unroll
+      for (int v = 0; v < KCH / VN; ++v) rt[a][v] = t_ok[a] ? src[v] : V{};
+    }
+  };
 
   acc_t acc[2][IC][IK];
 #pragma unroll
-  for (int q = 0; q < 2; ++q)
+  for (int par = 0; par < 2; ++par)
 #pragma unroll
     for (int i = 0; i < IC; ++i)
 #pragma unroll
-      for (int j = 0; j < IK; ++j) acc[q][i][j] = acc_t{0, 0, 0, 0};
+      for (int j = 0; j < IK; ++j) acc[par][i][j] = acc_t{0, 0, 0, 0};
 
-  for (int r0 = 0; r0 < mi.L; r0 += KJ) {
-    for (int idx = tid; idx < 2 * KJ * BC; idx += 256) {
-      const int par = idx / (KJ * BC);
-      const int rem = idx - par * (KJ * BC);
-      const int rr = rem / BC;
-      const int cc = rem - rr * BC;
-      const int r = r0 + rr;
-      const int c = it.c0 + cc;
-      T v = 0;
-      if (r < mi.L && c < twoF) {
-        const RingInfo rg = p.rings[mi.first_ring + r];
-        v = four[((rg.frow + m) * 2 + par) * rowlen + c];
-      }
-      Xs[par][rr][cc] = v;
-    }
-    for (int idx = tid; idx < 2 * KJ * BK; idx += 256) {
-      const int par = idx / (KJ * BK);
-      const int rem = idx - par * (KJ * BK);
-      const int kb = rem / (KJ * KCH);
-      const int rem2 = rem - kb * (KJ * KCH);
-      const int rr = rem2 / KCH;
-      const int kk = rem2 - rr * KCH;
-      const int k = it.t0 + kb * KCH + kk;
-      const int64_t toff = par ? mi.toff[1] : mi.toff[0];
-      const int kp = par ? mi.Kp[1] : mi.Kp[0];
-      T v = 0;
-      if (k < kp) v = tab[toff + (int64_t)(k / KCH) * mi.Lp * KCH + (int64_t)(r0 + rr) * KCH + (k % KCH)];
-      Ts[par][rr][kb * KCH + kk] = v;
-    }
+  fetch(0);
+  for (int jc = 0; jc < nj; ++jc) {
+#pragma unroll
+    for (int a = 0; a < XU; ++a) *(V*)&Xs[x_par[a]][x_rr[a]][x_c[a]] = rx[a];
+#pragma unroll
+    for (int a = 0; a < TU; ++a)
+#pragma unroll
+      for (int v = 0; v < KCH / VN; ++v) *(V*)&Ts[t_par[a]][t_rr[a]][t_ch[a] * KCH + v * VN] = rt[a][v];
     __syncthreads();
+    if (jc + 1 < nj) fetch(jc + 1);
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
 #pragma unroll
       for (int ks = 0; ks < KJ / 4; ++ks) {
-        T a[IC], b[IK];
+        T av[IC], bv[IK];
 #pragma unroll
-        for (int i = 0; i < IC; ++i) a[i] = Xs[par][ks * 4 + (lane >> 4)][wr * WC + i * 16 + (lane & 15)];
+        for (int i = 0; i < IC; ++i) av[i] = Xs[par][ks * 4 + (lane >> 4)][wr * WC + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < IK; ++j) b[j] = Ts[par][ks * 4 + (lane >> 4)][wc * WK + j * 16 + (lane & 15)];
+        for (int j = 0; j < IK; ++j) bv[j] = Ts[par][ks * 4 + (lane >> 4)][wc * WK + j * 16 + (lane & 15)];
 #pragma unroll
         for (int i = 0; i < IC; ++i)
 #pragma unroll
-          for (int j = 0; j < IK; ++j) acc[par][i][j] = mfma16x16x4(a[i], b[j], acc[par][i][j]);
+          for (int j = 0; j < IK; ++j) acc[par][i][j] = mfma16x16x4(av[i], bv[j], acc[par][i][j]);
       }
     }
     __syncthreads();
@@ -245,21 +346,34 @@ __global__ __launch_bounds__(256) void legendre_direct_kernel(DevPlan p, const W
 
 #pragma unroll
   for (int par = 0; par < 2; ++par) {
+    const int K = par ? mi.K[1] : mi.K[0];
 #pragma unroll
-    for (int i = 0; i < IC; ++i) {
+    for (int j = 0; j < IK; ++j) {
+      const int k = it.t0 + wc * WK + j * 16 + (lane & 15);
+      if (k >= K) continue;
+      C2* dst = (C2*)spec + (mi.spec_off + 2 * k + par);
 #pragma unroll
-      for (int j = 0; j < IK; ++j) {
-        const int k = it.t0 + wc * WK + j * 16 + (lane & 15);
-        if (k >= mi.K[par]) continue;
-        const int n = m + 2 * k + par;
+      for (int i = 0; i < IC; ++i) {
+        if constexpr (sizeof(T) == 4) {
+          // rows 4 (l/16) + e: e = 0, 1 and e = 2, 3 are (re, im) of two fields
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int c = it.c0 + wr * WC + i * 16 + acc_row<T>(lane, e);
-          if (c < twoF) {
-            const int f = c >> 1;
-            T v = acc[par][i][j][e];
-            if (m == 0 && (c & 1)) v = 0;
-            spec[((int64_t)f * p.nspec + mi.spec_off + (n - m)) * 2 + (c & 1)] = v;
+          for (int e = 0; e < 4; e += 2) {
+            const int c = it.c0 + wr * WC + i * 16 + 4 * (lane >> 4) + e;
+            if (c < twoF) {
+              C2 v = C2{acc[par][i][j][e], acc[par][i][j][e + 1]};
+              if (m == 0) v.y = 0;
+              dst[(int64_t)(c >> 1) * p.nspec] = v;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = it.c0 + wr * WC + i * 16 + acc_row<T>(lane, e);
+            if (c < twoF) {
+              T v = acc[par][i][j][e];
+              if (m == 0 && (c & 1)) v = 0;
+              ((T*)(dst + (int64_t)(c >> 1) * p.nspec))[c & 1] = v;
+            }
           }
         }
       }
@@ -271,8 +385,8 @@ __global__ __launch_bounds__(256) void legendre_direct_kernel(DevPlan p, const W
 // Tile shapes and launchers
 // ---------------------------------------------------------------------------
 
-constexpr int INV64_BM = 64, INV64_BN = 64, DIR64_BC = 64, DIR64_BK = 64;
-constexpr int INV32_BM = 128, INV32_BN = 128, DIR32_BC = 128, DIR32_BK = 64;
+constexpr int INV64_BM = 64, INV64_BN = 64, INV64_KI = 16, DIR64_BC = 64, DIR64_BK = 64, DIR64_KJ = 16;
+constexpr int INV32_BM = 128, INV32_BN = 128, INV32_KI = 16, DIR32_BC = 128, DIR32_BK = 64, DIR32_KJ = 16;
 
 void legendre_tiles(int prec, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols) {
   if (prec == SHT_FP64) {
@@ -292,10 +406,10 @@ hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* i
                                    const void* spec, void* four, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (prec == SHT_FP64)
-    hipLaunchKernelGGL((legendre_inverse_kernel<double, INV64_BM, INV64_BN>), dim3(nitems), dim3(256), 0, s, p,
+    hipLaunchKernelGGL((legendre_inverse_kernel<double, INV64_BM, INV64_BN, INV64_KI>), dim3(nitems), dim3(256), 0, s, p,
                        items, (const double*)spec, (double*)four);
   else if (prec == SHT_FP32)
-    hipLaunchKernelGGL((legendre_inverse_kernel<float, INV32_BM, INV32_BN>), dim3(nitems), dim3(256), 0, s, p,
+    hipLaunchKernelGGL((legendre_inverse_kernel<float, INV32_BM, INV32_BN, INV32_KI>), dim3(nitems), dim3(256), 0, s, p,
                        items, (const float*)spec, (float*)four);
   else
     return hipErrorNotSupported;
@@ -306,10 +420,10 @@ hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* it
                                   const void* four, void* spec, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (prec == SHT_FP64)
-    hipLaunchKernelGGL((legendre_direct_kernel<double, DIR64_BC, DIR64_BK>), dim3(nitems), dim3(256), 0, s, p,
+    hipLaunchKernelGGL((legendre_direct_kernel<double, DIR64_BC, DIR64_BK, DIR64_KJ>), dim3(nitems), dim3(256), 0, s, p,
                        items, (const double*)four, (double*)spec);
   else if (prec == SHT_FP32)
-    hipLaunchKernelGGL((legendre_direct_kernel<float, DIR32_BC, DIR32_BK>), dim3(nitems), dim3(256), 0, s, p,
+    hipLaunchKernelGGL((legendre_direct_kernel<float, DIR32_BC, DIR32_BK, DIR32_KJ>), dim3(nitems), dim3(256), 0, s, p,
                        items, (const float*)four, (float*)spec);
   else
     return hipErrorNotSupported;
