@@ -36,19 +36,22 @@ bool five_smooth(int64_t x) {
   return x == 1;
 }
 
-// Radix sequence for a 5-smooth length: as many 4s as possible, then 2, 3, 5.
+// Radix sequence for a 5-smooth length, fewest passes first: the power of
+// two as 16s plus one 2, 4 or 8; the power of three as 9s plus one 3; 5s.
 std::vector<int> radices(int L) {
   std::vector<int> r;
-  int x = L;
-  while (x % 4 == 0) {
-    r.push_back(4);
-    x /= 4;
-  }
+  int x = L, e2 = 0;
   while (x % 2 == 0) {
-    r.push_back(2);
     x /= 2;
+    ++e2;
   }
-  while (x % 3 == 0) {
+  for (; e2 >= 4; e2 -= 4) r.push_back(16);
+  if (e2 > 0) r.push_back(1 << e2);
+  while (x % 9 == 0) {
+    r.push_back(9);
+    x /= 9;
+  }
+  if (x % 3 == 0) {
     r.push_back(3);
     x /= 3;
   }
@@ -168,7 +171,7 @@ int build_host(sht_plan_s* p) {
     const int h = r.nlon / 2;
     r.cls = (int)(std::lower_bound(hs.begin(), hs.end(), h) - hs.begin());
     const FftClass& c = p->classes[r.cls];
-    p->lds_syn = std::max(p->lds_syn, (size_t)c.L * csize);
+    p->lds_syn = std::max(p->lds_syn, fft_lds_bytes(p->prec, c.L, -1));
     p->lds_ana = std::max(p->lds_ana, fft_lds_bytes(p->prec, c.L, r.mmax));
   }
   if (p->lds_ana > 160 * 1024) return SHT_EUNSUPPORTED;

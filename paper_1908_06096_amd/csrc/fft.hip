@@ -49,7 +49,14 @@ __device__ inline C cscale(C a, T s) {
   return C{a.x * s, a.y * s};
 }
 
-// Forward DFT of R points in registers.
+// LDS index of FFT element i: one complex slot of padding after every 16
+// elements, so that the strided stores of a Stockham pass (stride R or Ns R
+// elements across lanes) spread over the banks instead of piling onto a few.
+__device__ inline int lds_ix(int i) { return i + (i >> 4); }
+
+// Forward DFT of R points in registers.  Radices 8, 9 and 16 are built from
+// smaller ones by one Cooley-Tukey step (even/odd halves for 8 and 16,
+// 3 x 3 for 9).
 template <typename T, int R>
 __device__ inline void butterfly(typename V2T<T>::type* v) {
   typedef typename V2T<T>::type C;
@@ -89,32 +96,90 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
     v[4] = csub(a1, cmul_negi(b1));
     v[2] = cadd(a2, cmul_negi(b2));
     v[3] = csub(a2, cmul_negi(b2));
+  } else if constexpr (R == 8 || R == 16) {
+    constexpr int H = R / 2;
+    C e[H], o[H];
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      e[k] = v[2 * k];
+      o[k] = v[2 * k + 1];
+    }
+    butterfly<T, H>(e);
+    butterfly<T, H>(o);
+    // o[k] *= exp(-2 pi i k / R)
+    constexpr double c16[8] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                               0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613};
+    constexpr double s16[8] = {0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613,
+                               1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173};
+#pragma unroll
+    for (int k = 1; k < H; ++k) {
+      const int q = k * (16 / R);
+      o[k] = cmul(o[k], C{(T)c16[q], (T)-s16[q]});
+    }
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      v[k] = cadd(e[k], o[k]);
+      v[k + H] = csub(e[k], o[k]);
+    }
+  } else if constexpr (R == 9) {
+    // X[k1 + 3 k2] = sum_n2 w9^(n2 k1) w3^(n2 k2) DFT3_n1(v[3 n1 + n2])[k1]
+    const T c1 = (T)0.76604444311897803520, s1 = (T)0.64278760968653932632;  // 2 pi / 9
+    const T c2 = (T)0.17364817766693034885, s2 = (T)0.98480775301220805936;  // 4 pi / 9
+    const T c4 = (T)-0.93969262078590838405, s4 = (T)0.34202014332566873304; // 8 pi / 9
+    C y[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+      C t[3] = {v[n2], v[3 + n2], v[6 + n2]};
+      butterfly<T, 3>(t);
+      y[n2][0] = t[0];
+      y[n2][1] = t[1];
+      y[n2][2] = t[2];
+    }
+    y[1][1] = cmul(y[1][1], C{c1, -s1});
+    y[1][2] = cmul(y[1][2], C{c2, -s2});
+    y[2][1] = cmul(y[2][1], C{c2, -s2});
+    y[2][2] = cmul(y[2][2], C{c4, -s4});
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      C t[3] = {y[0][k1], y[1][k1], y[2][k1]};
+      butterfly<T, 3>(t);
+      v[k1] = t[0];
+      v[k1 + 3] = t[1];
+      v[k1 + 6] = t[2];
+    }
   }
 }
 
+// What the last pass of a transform does with its outputs.
+enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2 };
+
 // One Stockham pass of radix R over L points in LDS, after Ns points have
-// been combined: butterfly b reads buf[b + r L/R] (twiddled by
-// exp(-2 pi i r (b mod Ns) / (Ns R))) and writes buf[(b / Ns) Ns R + b mod Ns
-// + r Ns].  All reads of the pass land in registers before the barrier, so
-// one buffer suffices.
-template <typename T, int R>
-__device__ inline void stockham_pass(typename V2T<T>::type* buf, int L, int Ns,
-                                     const typename V2T<T>::type* roots) {
+// been combined: butterfly b reads x[b + r L/R], twiddles input r by
+// exp(-2 pi i r (b mod Ns) / (Ns R)) (the pass's table holds these at
+// (b mod Ns)(R - 1) + r - 1, so lanes with consecutive b read consecutive
+// entries) and writes y[(b / Ns) Ns R + b mod Ns + r Ns].  All reads of the pass land in registers before the barrier, so
+// one LDS buffer suffices.  OUT_KHAT stores conj(y khat) and OUT_CHIRP
+// stores c_q conj(y_q) for q < h (the element-wise steps of the chirp-z
+// convolution).  Each instantiation is its own non-inlined function so that
+// its registers are allocated for it alone.
+template <typename T, int R, int MODE>
+__device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, int Ns,
+                                           const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
+                                           int h) {
   typedef typename V2T<T>::type C;
   constexpr int MAXB = FFT_REGS / R;
   const int nb = L / R;
-  const int tw = L / (Ns * R);
   C v[MAXB][R];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     const int b = threadIdx.x + i * FFT_THREADS;
     if (b < nb) {
-      const int k = b % Ns;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * nb];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_ix(b + r * nb)];
       if (Ns > 1) {
+        const C* t = tw + (b % Ns) * (R - 1) - 1;
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], roots[r * k * tw]);
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], t[r]);
       }
     }
   }
@@ -125,135 +190,193 @@ __device__ inline void stockham_pass(typename V2T<T>::type* buf, int L, int Ns,
     if (b < nb) {
       butterfly<T, R>(v[i]);
       const int k = b % Ns;
-      const int d = (b / Ns) * Ns * R + k;
+      const int d = (b - k) * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[d + r * Ns] = v[i][r];
+      for (int r = 0; r < R; ++r) {
+        const int o = d + r * Ns;
+        if constexpr (MODE == OUT_PLAIN) {
+          buf[lds_ix(o)] = v[i][r];
+        } else if constexpr (MODE == OUT_KHAT) {
+          buf[lds_ix(o)] = cconj(cmul(v[i][r], aux[o]));
+        } else {
+          if (o < h) buf[lds_ix(o)] = cmul(aux[o], cconj(v[i][r]));
+        }
+      }
     }
   }
   __syncthreads();
 }
 
-// Forward DFT of L points held in LDS (result in natural order, in place).
-template <typename T>
-__device__ void fft_lds(typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
-                        const typename V2T<T>::type* roots) {
+template <typename T, int MODE>
+__device__ inline void pass_dispatch(int R, typename V2T<T>::type* buf, int L, int Ns,
+                                     const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h) {
+  switch (R) {
+    case 16: stockham_pass<T, 16, MODE>(buf, L, Ns, tw, aux, h); break;
+    case 9: stockham_pass<T, 9, MODE>(buf, L, Ns, tw, aux, h); break;
+    case 8: stockham_pass<T, 8, MODE>(buf, L, Ns, tw, aux, h); break;
+    case 5: stockham_pass<T, 5, MODE>(buf, L, Ns, tw, aux, h); break;
+    case 4: stockham_pass<T, 4, MODE>(buf, L, Ns, tw, aux, h); break;
+    case 3: stockham_pass<T, 3, MODE>(buf, L, Ns, tw, aux, h); break;
+    default: stockham_pass<T, 2, MODE>(buf, L, Ns, tw, aux, h); break;
+  }
+}
+
+// Forward DFT of L points held in LDS (natural order in and out); the last
+// pass applies MODE.
+template <typename T, int MODE>
+__device__ void fft_lds(typename V2T<T>::type* buf, int L, int nrad, const int32_t* rad,
+                        const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h) {
   int Ns = 1;
-  for (int q = 0; q < c.nrad; ++q) {
+  for (int q = 0; q < nrad; ++q) {
     const int R = rad[q];
-    if (R == 4) stockham_pass<T, 4>(buf, c.L, Ns, roots);
-    else if (R == 2) stockham_pass<T, 2>(buf, c.L, Ns, roots);
-    else if (R == 3) stockham_pass<T, 3>(buf, c.L, Ns, roots);
-    else stockham_pass<T, 5>(buf, c.L, Ns, roots);
+    if (q == nrad - 1) pass_dispatch<T, MODE>(R, buf, L, Ns, tw, aux, h);
+    else pass_dispatch<T, OUT_PLAIN>(R, buf, L, Ns, tw, aux, h);
+    tw += Ns * (R - 1);
     Ns *= R;
   }
 }
 
-// Forward complex DFT of length h of buf[0..h); the result is left in
-// buf[0..h).  For chirp-z classes buf must hold L entries.
+// Forward complex DFT of length h.  On entry buf[t] holds z_t, t < h,
+// already multiplied by the chirp c_t for chirp-z classes, whose entries
+// h <= t < L must be zero.  On exit buf[q], q < h, holds Z_q.  Chirp-z:
+// A = DFT_L(a), B = conj(A khat), Z_q = c_q conj(DFT_L(B))_q.
 template <typename T>
 __device__ void dft_h(typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
                       const typename V2T<T>::type* tabs) {
-  typedef typename V2T<T>::type C;
-  const C* roots = tabs + c.root_off;
+  const typename V2T<T>::type* tw = tabs + c.root_off;
   if (!c.bluestein) {
-    fft_lds<T>(buf, c, rad, roots);
+    fft_lds<T, OUT_PLAIN>(buf, c.L, c.nrad, rad, tw, nullptr, c.h);
     return;
   }
-  const C* chirp = tabs + c.chirp_off;
-  const C* khat = tabs + c.khat_off;
-  for (int t = threadIdx.x; t < c.L; t += FFT_THREADS) buf[t] = (t < c.h) ? cmul(buf[t], chirp[t]) : C{0, 0};
-  __syncthreads();
-  fft_lds<T>(buf, c, rad, roots);
-  for (int u = threadIdx.x; u < c.L; u += FFT_THREADS) buf[u] = cconj(cmul(buf[u], khat[u]));
-  __syncthreads();
-  fft_lds<T>(buf, c, rad, roots);
-  for (int q = threadIdx.x; q < c.h; q += FFT_THREADS) buf[q] = cmul(chirp[q], cconj(buf[q]));
-  __syncthreads();
+  fft_lds<T, OUT_KHAT>(buf, c.L, c.nrad, rad, tw, tabs + c.khat_off, c.h);
+  fft_lds<T, OUT_CHIRP>(buf, c.L, c.nrad, rad, tw, tabs + c.chirp_off, c.h);
 }
 
 constexpr int FFT_FCHUNK = 16;
+constexpr int NUM_XCD = 8;
+
+// Work-group -> (work item, field).  One work item is a ring (pair) and a
+// chunk of FFT_FCHUNK fields that share cache lines of the Fourier buffer
+// (fields are its innermost index).  Work groups are handed to the XCDs
+// round-robin by id, so the FFT_FCHUNK fields of an item get ids that are
+// congruent modulo NUM_XCD and adjacent in dispatch order: they run on one
+// XCD at the same time and their strided accesses meet in that XCD's L2.
+__device__ inline bool decode_block(int nitems, int* item, int* slot) {
+  const int bid = blockIdx.x;
+  const int grp = bid / (NUM_XCD * FFT_FCHUNK);
+  const int r = bid - grp * (NUM_XCD * FFT_FCHUNK);
+  *item = grp * NUM_XCD + r % NUM_XCD;
+  *slot = r / NUM_XCD;
+  return *item < nitems;
+}
+
+size_t fft_grid_blocks(int nitems) {
+  return (size_t)((nitems + NUM_XCD - 1) / NUM_XCD) * NUM_XCD * FFT_FCHUNK;
+}
 
 // ---------------------------------------------------------------------------
-// Synthesis: ring j, fields [f0, f0 + FFT_FCHUNK).
+// Synthesis: ring j, one field of the chunk [f0, f0 + FFT_FCHUNK).
 //   X_m = c_m for m <= mmax_j (Im c_0 dropped), 0 above, Nyquist 0;
 //   Z_q = (X_q + conj X_{h-q}) + i w^q (X_q - conj X_{h-q}),  w = exp(2 pi i / n);
-//   z = inverse DFT_h(Z) (no 1/h);  g_{2t} = Re z_t,  g_{2t+1} = Im z_t.
+//   z = inverse DFT_h(Z) = conj(DFT_h(conj Z));  g_{2t} = Re z_t,  g_{2t+1} = Im z_t.
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void fourier_synthesis_kernel(DevPlan p, const int2* items,
+__global__ __launch_bounds__(FFT_THREADS) void fourier_synthesis_kernel(DevPlan p, const int2* items, int nitems,
                                                                         const T* __restrict__ four,
                                                                         T* __restrict__ grid) {
   typedef typename V2T<T>::type C;
   extern __shared__ __align__(16) unsigned char smem[];
-  C* buf = (C*)smem;
-  const int2 it = items[blockIdx.x];
+  int item, slot;
+  if (!decode_block(nitems, &item, &slot)) return;
+  const int2 it = items[item];
+  const int f = it.y + slot;
+  if (f >= p.F) return;
   const RingInfo ri = p.rings[it.x];
   const FftClass cl = p.classes[ri.cls];
+  const int32_t* rad = p.classes[ri.cls].rad;
   const C* tabs = (const C*)p.fft;
+  C* buf = (C*)smem;
   const C* post = tabs + cl.post_off;
+  const C* chirp = tabs + cl.chirp_off;
   const C* fc = (const C*)four;
-  const int h = cl.h, mmax = ri.mmax;
-  const int fend = min(it.y + FFT_FCHUNK, p.F);
-  for (int f = it.y; f < fend; ++f) {
-    const C* cf = fc + ri.frow * (int64_t)p.Fp + f;
-    for (int q = threadIdx.x; q < h; q += FFT_THREADS) {
-      C xq = (q <= mmax) ? cf[(int64_t)q * p.Fp] : C{0, 0};
-      if (q == 0) xq.y = 0;
-      const int q2 = h - q;
-      const C xr = (q >= 1 && q2 <= mmax) ? cconj(cf[(int64_t)q2 * p.Fp]) : C{0, 0};
-      const C s = cadd(xq, xr);
-      const C d = csub(xq, xr);
-      const C om = cconj(post[q]);
-      const C t = cmul(om, d);
-      const C z = C{s.x - t.y, s.y + t.x};  // s + i t
-      buf[q] = cconj(z);
+  const int h = cl.h, mmax = ri.mmax, L = cl.L;
+  const bool blue = cl.bluestein;
+  const int64_t Fp = p.Fp;
+  {
+    const C* cf = fc + ri.frow * Fp + f;
+    for (int q = threadIdx.x; q < (blue ? L : h); q += FFT_THREADS) {
+      C y = C{0, 0};
+      if (q < h) {
+        C xq = (q <= mmax) ? cf[q * Fp] : C{0, 0};
+        if (q == 0) xq.y = 0;
+        const int q2 = h - q;
+        const C xr = (q >= 1 && q2 <= mmax) ? cconj(cf[q2 * Fp]) : C{0, 0};
+        const C s = cadd(xq, xr);
+        const C t = cmul(cconj(post[q]), csub(xq, xr));
+        y = C{s.x - t.y, -(s.y + t.x)};  // conj(s + i t)
+        if (blue) y = cmul(y, chirp[q]);
+      }
+      buf[lds_ix(q)] = y;
     }
     __syncthreads();
-    dft_h<T>(buf, cl, p.classes[ri.cls].rad, tabs);
+    dft_h<T>(buf, cl, rad, tabs);
     T* g = grid + (int64_t)f * p.npts + ri.goff;
     for (int t = threadIdx.x; t < h; t += FFT_THREADS) {
-      const C r = buf[t];
-      g[2 * t] = r.x;
-      g[2 * t + 1] = -r.y;
+      const C y = buf[lds_ix(t)];
+      g[2 * t] = y.x;
+      g[2 * t + 1] = -y.y;
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Analysis: north ring j and its mirror, fields [f0, f0 + FFT_FCHUNK).
+// Analysis: north ring j and its mirror, one field of the chunk [f0, f0 + FFT_FCHUNK).
 //   Z = DFT_h(z),  X_m = (Z_m + conj Z_{h-m})/2 - (i/2) w^{-m} (Z_m - conj Z_{h-m}),
 //   chat_m = X_m / n;  S = w_j (chat_N + chat_S),  A = w_j (chat_N - chat_S).
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void fourier_analysis_kernel(DevPlan p, const int2* items,
+__global__ __launch_bounds__(FFT_THREADS) void fourier_analysis_kernel(DevPlan p, const int2* items, int nitems,
                                                                        const T* __restrict__ grid,
                                                                        T* __restrict__ four) {
   typedef typename V2T<T>::type C;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int2 it = items[blockIdx.x];
+  int item, slot;
+  if (!decode_block(nitems, &item, &slot)) return;
+  const int2 it = items[item];
+  const int f = it.y + slot;
+  if (f >= p.F) return;
   const RingInfo rn = p.rings[it.x];
   const RingInfo rs = p.rings[rn.mirror];
   const FftClass cl = p.classes[rn.cls];
-  C* buf = (C*)smem;
-  C* keep = buf + cl.L;
+  const int32_t* rad = p.classes[rn.cls].rad;
   const C* tabs = (const C*)p.fft;
+  C* buf = (C*)smem;
+  C* keep = buf + lds_ix(cl.L) + 1;
   const C* post = tabs + cl.post_off;
+  const C* chirp = tabs + cl.chirp_off;
   C* fc = (C*)four;
-  const int h = cl.h, mmax = rn.mmax;
+  const int h = cl.h, mmax = rn.mmax, L = cl.L;
+  const bool blue = cl.bluestein;
   const T scale = (T)(p.w[it.x] / (double)rn.nlon);
-  const int fend = min(it.y + FFT_FCHUNK, p.F);
-  for (int f = it.y; f < fend; ++f) {
+  {
     for (int side = 0; side < 2; ++side) {
       const T* g = grid + (int64_t)f * p.npts + (side ? rs.goff : rn.goff);
-      for (int t = threadIdx.x; t < h; t += FFT_THREADS) buf[t] = C{g[2 * t], g[2 * t + 1]};
+      for (int t = threadIdx.x; t < (blue ? L : h); t += FFT_THREADS) {
+        C z = C{0, 0};
+        if (t < h) {
+          z = C{g[2 * t], g[2 * t + 1]};
+          if (blue) z = cmul(z, chirp[t]);
+        }
+        buf[lds_ix(t)] = z;
+      }
       __syncthreads();
-      dft_h<T>(buf, cl, p.classes[rn.cls].rad, tabs);
+      dft_h<T>(buf, cl, rad, tabs);
       for (int m = threadIdx.x; m <= mmax; m += FFT_THREADS) {
-        const C zm = buf[m];
-        const C zr = cconj(buf[m == 0 ? 0 : h - m]);
+        const C zm = buf[lds_ix(m)];
+        const C zr = cconj(buf[lds_ix(m == 0 ? 0 : h - m)]);
         const C s = cadd(zm, zr);
         const C d = csub(zm, zr);
         const C t = cmul(post[m], d);
@@ -277,18 +400,19 @@ __global__ __launch_bounds__(FFT_THREADS) void fourier_analysis_kernel(DevPlan p
 
 size_t fft_lds_bytes(int prec, int L, int mmax) {
   const size_t c = (prec == SHT_FP64) ? 16 : 8;
-  return c * ((size_t)L + (size_t)mmax + 1);
+  const size_t padded = (size_t)L + (size_t)L / 16 + 1;
+  return c * (padded + (mmax >= 0 ? (size_t)mmax + 1 : 0));
 }
 
 hipError_t launch_fourier_synthesis(const DevPlan& p, int prec, const int2* items, int nitems, size_t lds,
                                     const void* four, void* grid, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (prec == SHT_FP64)
-    hipLaunchKernelGGL(fourier_synthesis_kernel<double>, dim3(nitems), dim3(FFT_THREADS), lds, s, p, items,
-                       (const double*)four, (double*)grid);
+    hipLaunchKernelGGL(fourier_synthesis_kernel<double>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
+                       items, nitems, (const double*)four, (double*)grid);
   else
-    hipLaunchKernelGGL(fourier_synthesis_kernel<float>, dim3(nitems), dim3(FFT_THREADS), lds, s, p, items,
-                       (const float*)four, (float*)grid);
+    hipLaunchKernelGGL(fourier_synthesis_kernel<float>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
+                       items, nitems, (const float*)four, (float*)grid);
   return hipGetLastError();
 }
 
@@ -296,11 +420,11 @@ hipError_t launch_fourier_analysis(const DevPlan& p, int prec, const int2* items
                                    const void* grid, void* four, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (prec == SHT_FP64)
-    hipLaunchKernelGGL(fourier_analysis_kernel<double>, dim3(nitems), dim3(FFT_THREADS), lds, s, p, items,
-                       (const double*)grid, (double*)four);
+    hipLaunchKernelGGL(fourier_analysis_kernel<double>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
+                       items, nitems, (const double*)grid, (double*)four);
   else
-    hipLaunchKernelGGL(fourier_analysis_kernel<float>, dim3(nitems), dim3(FFT_THREADS), lds, s, p, items,
-                       (const float*)grid, (float*)four);
+    hipLaunchKernelGGL(fourier_analysis_kernel<float>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
+                       items, nitems, (const float*)grid, (float*)four);
   return hipGetLastError();
 }
 

@@ -52,7 +52,8 @@ struct FftClass {
   int32_t bluestein;
   int32_t nrad;
   int32_t rad[FFT_MAX_RADICES];
-  int64_t root_off;   // L complex roots exp(-2 pi i q / L)
+  int64_t root_off;   // L - 1 twiddles, pass after pass: exp(-2 pi i r k / (Ns R)) at
+                      // k (R - 1) + r - 1 of the pass table (k < Ns, 1 <= r < R)
   int64_t post_off;   // h complex values exp(-2 pi i q / (2h))
   int64_t chirp_off;  // h complex values exp(-i pi t^2 / h)      (bluestein)
   int64_t khat_off;   // L complex: DFT_L of the conjugate chirp / L (bluestein)

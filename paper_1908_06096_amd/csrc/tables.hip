@@ -169,7 +169,8 @@ hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& m
 // ---------------------------------------------------------------------------
 // FFT tables, one work group per class.  Angles are reduced exactly in
 // integer arithmetic before one float64 sincospi call:
-//   roots  exp(-2 pi i q / L)                      q < L
+//   twiddles, pass after pass (radix R after Ns points are combined):
+//          exp(-2 pi i r k / (Ns R))             k < Ns, 1 <= r < R
 //   post   exp(-2 pi i q / (2h))                   q < h
 //   chirp  exp(-i pi (t^2 mod 2h) / h)             t < h
 //   khat_u = (1/L) sum_{|t| < h} exp(+i pi t^2/h) exp(-2 pi i u t / L)
@@ -188,10 +189,20 @@ template <typename T>
 __global__ void fft_tables_kernel(const FftClass* cls, T* fft) {
   const FftClass c = cls[blockIdx.x];
   const int L = c.L, h = c.h;
-  for (int q = threadIdx.x; q < L; q += blockDim.x) {
-    double sn, cs;
-    sincospi(-2.0 * (double)q / (double)L, &sn, &cs);
-    put_c(fft, c.root_off + q, cs, sn);
+  int64_t off = c.root_off;
+  int Ns = 1;
+  for (int pass = 0; pass < c.nrad; ++pass) {
+    const int R = c.rad[pass];
+    const int NR = Ns * R;
+    for (int e = threadIdx.x; e < Ns * (R - 1); e += blockDim.x) {
+      const int k = e / (R - 1);
+      const int r = e % (R - 1) + 1;
+      double sn, cs;
+      sincospi(-2.0 * (double)((r * k) % NR) / (double)NR, &sn, &cs);
+      put_c(fft, off + e, cs, sn);
+    }
+    off += Ns * (R - 1);
+    Ns = NR;
   }
   for (int q = threadIdx.x; q < h; q += blockDim.x) {
     double sn, cs;
