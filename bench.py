@@ -12,7 +12,11 @@ Prints one JSON line (metric, value = field-transforms/s, per-stage timings,
 the roofline of the dominant kernel measured with HIP events on the stream the
 kernels run on, and the FP64 CPU oracle's rate on a bounded sample).
 
-    python bench.py [--steps K] [--warmup W] [--precision fp32|fp64]
+    python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|fp64]
+                    [--variants bf16x3,fp64]
+
+The main precision is timed over K steps; each variant (other precisions of
+the same workload, for comparison) over min(K, 3) steps.
 """
 
 import argparse
@@ -86,11 +90,56 @@ def stage_bytes(N, geo, F, elem, tab_elem):
     }
 
 
+_INPUTS = {}
+
+
+def host_inputs(workload, seed=0):
+    """Seeded spectral coefficients of every field, drawn once (float64)."""
+    from paper_1908_06096_amd.inputs import spectral_coefficients
+
+    key = (workload, seed)
+    if key not in _INPUTS:
+        N, _grid, F = WORKLOADS[workload]
+        t0 = time.time()
+        _INPUTS[key] = spectral_coefficients(N, F, seed=seed, dtype=np.float64)
+        log(f"[bench] drew inputs for {workload} ({time.time() - t0:.1f} s)")
+    return _INPUTS[key]
+
+
+def stage_report(N, geo, F, precision, per_stage_ms):
+    """Per-stage rates against their roofs and the roofline of the slowest
+    stage.  Legendre products: algorithmic flops (bf16x3 issues three BF16
+    products per multiply-add and is measured against the BF16 peak, with
+    the FP32-equivalent rate alongside); FFTs: algorithmic HBM bytes."""
+    elem = 8 if precision == "fp64" else 4
+    flops = legendre_flops(N, geo, F)
+    nbytes = stage_bytes(N, geo, F, elem, elem)
+    mult, peak = {"fp64": (1, PEAK["fp64"]), "fp32": (1, PEAK["fp32"]), "bf16x3": (3, PEAK["bf16"])}[precision]
+    stages = {}
+    for name, ms in per_stage_ms.items():
+        if name.startswith("legendre"):
+            ach = mult * flops / (ms * 1e-3)
+            stages[name] = {"ms": ms, "bound": "mfma", "achieved_tflops": ach / 1e12, "frac": ach / peak,
+                            "fp32_equiv_tflops": flops / (ms * 1e-3) / 1e12,
+                            "hbm_gbs": nbytes[name] / (ms * 1e-3) / 1e9}
+        else:
+            ach = nbytes[name] / (ms * 1e-3)
+            stages[name] = {"ms": ms, "bound": "hbm", "achieved_gbs": ach / 1e9, "frac": ach / PEAK["hbm"]}
+    dom = max(per_stage_ms, key=per_stage_ms.get)
+    d = stages[dom]
+    if d["bound"] == "mfma":
+        roof = {"kernel": dom, "bound": "mfma", "achieved": d["achieved_tflops"], "peak": peak / 1e12,
+                "unit": "TFLOP/s", "frac": d["frac"], "traffic": None}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": d["achieved_gbs"], "peak": PEAK["hbm"] / 1e9,
+                "unit": "GB/s", "frac": d["frac"], "traffic": None}
+    return stages, roof
+
+
 def run_gpu(workload, precision, steps, warmup, seed=0):
     import torch
 
     from paper_1908_06096_amd import sht
-    from paper_1908_06096_amd.inputs import spectral_coefficients
 
     N, grid, F = WORKLOADS[workload]
     torch.cuda.set_device(0)
@@ -99,11 +148,9 @@ def run_gpu(workload, precision, steps, warmup, seed=0):
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     log(f"[bench] plan {workload} {precision}: {plan_s:.2f} s, tables {plan.info.table_bytes / 1e9:.2f} GB")
-    dt = np.float64 if precision == "fp64" else np.float32
+    dt = torch.float64 if precision == "fp64" else torch.float32
     t0 = time.time()
-    s = spectral_coefficients(N, F, seed=seed, dtype=dt)
-    spec = torch.from_numpy(s).cuda()
-    del s
+    spec = torch.from_numpy(host_inputs(workload, seed)).to(device="cuda", dtype=dt)
     grid_t = plan.empty_grid()
     back = plan.empty_spec()
     ws = plan.empty_workspace()
@@ -171,7 +218,7 @@ def oracle_sample_error(res, precision, seed=0, nrings=4):
 
     N, grid = res["N"], res["grid"]
     dt = np.float64 if precision == "fp64" else np.float32
-    s = spectral_coefficients(N, 1, seed=seed, dtype=dt)
+    s = spectral_coefficients(N, 1, seed=seed, dtype=np.float64).astype(dt)
     spec_c = s[..., 0].astype(np.float64) + 1j * s[..., 1].astype(np.float64)
     geo = oracle.grid_geometry(N, grid)
     rings = np.linspace(0, geo["nlat"] - 1, nrings).astype(int)
@@ -244,7 +291,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="TCo1279-O1280-F411", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp64"])
+    ap.add_argument("--variants", default="bf16x3,fp64",
+                    help="comma-separated other precisions to time on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
@@ -256,27 +305,7 @@ def main():
     res = run_gpu(args.workload, args.precision, args.steps, args.warmup)
     N, F = res["N"], res["F"]
     geo = geometry_counts(N, res["grid"])
-    elem = 8 if args.precision == "fp64" else 4
-    flops = legendre_flops(N, geo, F)
-    nbytes = stage_bytes(N, geo, F, elem, elem)
-    st = res["per_stage_ms"]
-    stages = {}
-    for name, ms in st.items():
-        if name.startswith("legendre"):
-            ach = flops / (ms * 1e-3)
-            stages[name] = {"ms": ms, "bound": "mfma", "achieved_tflops": ach / 1e12,
-                            "frac": ach / PEAK[args.precision], "hbm_gbs": nbytes[name] / (ms * 1e-3) / 1e9}
-        else:
-            ach = nbytes[name] / (ms * 1e-3)
-            stages[name] = {"ms": ms, "bound": "hbm", "achieved_gbs": ach / 1e9, "frac": ach / PEAK["hbm"]}
-    dom = max(st, key=st.get)
-    d = stages[dom]
-    if d["bound"] == "mfma":
-        roof = {"kernel": dom, "bound": "mfma", "achieved": d["achieved_tflops"], "peak": PEAK[args.precision] / 1e12,
-                "unit": "TFLOP/s", "frac": d["frac"], "traffic": None}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": d["achieved_gbs"], "peak": PEAK["hbm"] / 1e9,
-                "unit": "GB/s", "frac": d["frac"], "traffic": None}
+    stages, roof = stage_report(N, geo, F, args.precision, res["per_stage_ms"])
 
     ms_per_step = res["total_ms"] / args.steps
     value = 2.0 * F * args.steps / (res["total_ms"] * 1e-3)
@@ -291,7 +320,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": {"fp32": "f32", "bf16x3": "bf16x3-f32acc", "fp64": "f64"}[args.precision],
         "data": "synthetic",
         "config": {"workload": args.workload, "truncation": N, "grid": res["grid"], "fields": F,
                    "precision": args.precision, "step": "inverse + direct of all fields"},
@@ -303,6 +332,28 @@ def main():
         out["oracle_rel_l2_sample"] = oracle_sample_error(res, args.precision)
         log(f"[bench] oracle sample error {out['oracle_rel_l2_sample']:.2e}")
     res["plan"].close()
+    del res
+    variants = {}
+    for prec in [v for v in args.variants.split(",") if v and v != args.precision]:
+        import torch
+
+        torch.cuda.empty_cache()
+        r = run_gpu(args.workload, prec, min(args.steps, 3), 1)
+        st, rf = stage_report(N, geo, F, prec, r["per_stage_ms"])
+        variants[prec] = {
+            "value": 2.0 * F * r["steps"] / (r["total_ms"] * 1e-3),
+            "ms_per_step": r["total_ms"] / r["steps"],
+            "steps": r["steps"],
+            "roofline": rf,
+            "stages": st,
+            "round_trip_rel_l2": r["round_trip_rel_l2"],
+        }
+        if not args.no_oracle_check:
+            variants[prec]["oracle_rel_l2_sample"] = oracle_sample_error(r, prec)
+        r["plan"].close()
+        del r
+    if variants:
+        out["variants"] = variants
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(args.workload)

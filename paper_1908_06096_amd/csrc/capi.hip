@@ -317,7 +317,6 @@ int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int 
   if (truncation < 1 || nfields < 1) return SHT_EINVAL;
   if (grid != SHT_GRID_FULL && grid != SHT_GRID_OCTAHEDRAL) return SHT_EINVAL;
   if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_EINVAL;
-  if (precision == SHT_BF16X3) return SHT_EUNSUPPORTED;
   sht_plan_s* p = new (std::nothrow) sht_plan_s();
   if (!p) return SHT_ENOMEM;
   p->N = truncation;
@@ -407,7 +406,7 @@ size_t sht_workspace_size(sht_plan_t p) {
 
 int sht_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* stream) {
   if (!p || !spec || !four) return SHT_EINVAL;
-  HIP_TRY(launch_legendre_inverse(p->dp, p->prec, p->d_inv, (int)p->inv_items.size(), spec, four,
+  HIP_TRY(launch_legendre_inverse(p->dp, p->prec, p->d_inv, (int)p->inv_items.size(), p->tab_plane, spec, four,
                                   (hipStream_t)stream));
   return SHT_OK;
 }
@@ -428,7 +427,7 @@ int sht_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* strea
 
 int sht_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream) {
   if (!p || !spec || !four) return SHT_EINVAL;
-  HIP_TRY(launch_legendre_direct(p->dp, p->prec, p->d_dir, (int)p->dir_items.size(), four, spec,
+  HIP_TRY(launch_legendre_direct(p->dp, p->prec, p->d_dir, (int)p->dir_items.size(), p->tab_plane, four, spec,
                                  (hipStream_t)stream));
   return SHT_OK;
 }

@@ -382,11 +382,354 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(DevPlan p, cons
 }
 
 // ---------------------------------------------------------------------------
+// BF16 split precision.  Every operand x (float32) is split into
+// hi = bf16_rne(x) and lo = bf16_rne(x - hi); a product is accumulated in
+// float32 as lo*hi + hi*lo + hi*hi (the lo*lo term, below float32 rounding of
+// the result, is dropped).  MFMA 16x16x32 bf16: lane l holds 8 consecutive K
+// of row l % 16 of A (and of column l % 16 of B) starting at K = 8 (l / 16);
+// the output placement is that of the f32 16x16x4 instruction.  LDS rows
+// are K-contiguous so a lane's operand is one 16-byte read; rows are padded
+// by 8 elements so that 16 lanes reading 16 rows hit distinct banks.
+// ---------------------------------------------------------------------------
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16;
+
+__device__ inline f32x4 mfma_bf16(const uint4& a, const uint4& b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+__device__ inline u16 bf16_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (u16)(u >> 16);
+}
+
+__device__ inline void split_bf16(float x, u16* hi, u16* lo) {
+  *hi = bf16_bits(x);
+  *lo = bf16_bits(x - __uint_as_float(((uint32_t)*hi) << 16));
+}
+
+__device__ inline uint32_t pack2(u16 a, u16 b) { return (uint32_t)a | ((uint32_t)b << 16); }
+
+constexpr int BPAD = 8;
+
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(DevPlan p, const WorkItem* items,
+                                                                      int64_t plane,
+                                                                      const float* __restrict__ spec,
+                                                                      float* __restrict__ four) {
+  constexpr int KI = 32;                  // k of each parity per iteration
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int IM = WM / 16, IN = WN / 16;
+  constexpr int NC = KI / KCH;            // table chunks per parity per iteration
+  constexpr int AUNITS = 2 * 2 * NC * BM; // (plane, parity, chunk, row) units of 16 bytes
+  constexpr int AU = AUNITS / 256;
+  static_assert(BN / 2 * 4 == 256, "one thread per (field, quarter)");
+  __shared__ __align__(16) u16 As[2][2][BM][KI + BPAD];  // [plane][parity][row][k]
+  __shared__ __align__(16) u16 Bs[2][2][BN][KI + BPAD];  // [plane][parity][col][k]
+
+  const WorkItem it = items[blockIdx.x];
+  const MInfo mi = p.ms[it.m];
+  const int m = mi.m;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const u16* tab = (const u16*)p.tab;
+  const int twoF = 2 * p.F;
+  const int kpmax = mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1];
+  const int nk = (kpmax + KI - 1) / KI;
+
+  int a_pl[AU], a_par[AU], a_ch[AU], a_row[AU], a_nch[AU];
+  int64_t a_base[AU];
+  bool a_ok[AU];
+#pragma unroll
+  for (int a = 0; a < AU; ++a) {
+    const int u = tid + 256 * a;
+    a_row[a] = u % BM;
+    a_ch[a] = (u / BM) % NC;
+    a_par[a] = (u / (BM * NC)) % 2;
+    a_pl[a] = u / (BM * NC * 2);
+    a_nch[a] = (a_par[a] ? mi.Kp[1] : mi.Kp[0]) / KCH;
+    a_ok[a] = it.t0 + a_row[a] < mi.Lp;
+    a_base[a] = (a_pl[a] ? plane : 0) + (a_par[a] ? mi.toff[1] : mi.toff[0]) + (int64_t)a_ch[a] * mi.Lp * KCH +
+                (int64_t)(it.t0 + a_row[a]) * KCH;
+  }
+  const int64_t a_step = (int64_t)NC * mi.Lp * KCH;
+  // spectral: thread (field fi, quarter q) owns n - m in [2 KI kc + 16 q, + 16)
+  const int fi = tid >> 2;
+  const int q = tid & 3;
+  const int f = it.c0 / 2 + fi;
+  const bool f_ok = f < p.F;
+  const float2* sp = (const float2*)spec + ((int64_t)(f_ok ? f : 0) * p.nspec + mi.spec_off);
+
+  uint4 ra[AU];
+  float2 rb[16];
+  auto fetch = [&](int kc) {
+#pragma unroll
+    for (int a = 0; a < AU; ++a) {
+      const bool ok = a_ok[a] && (kc * NC + a_ch[a] < a_nch[a]);
+      ra[a] = ok ? *(const uint4*)(tab + a_base[a] + kc * a_step) : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int d = 2 * KI * kc + 16 * q + i;
+      float2 x = make_float2(0.f, 0.f);
+      if (f_ok && m + d <= p.N) x = sp[d];
+      if (m == 0) x.y = 0.f;
+      rb[i] = x;
+    }
+  };
+
+  f32x4 acc[2][IM][IN];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int i = 0; i < IM; ++i)
+#pragma unroll
+      for (int j = 0; j < IN; ++j) acc[par][i][j] = f32x4{0, 0, 0, 0};
+
+  fetch(0);
+  for (int kc = 0; kc < nk; ++kc) {
+#pragma unroll
+    for (int a = 0; a < AU; ++a) *(uint4*)&As[a_pl[a]][a_par[a]][a_row[a]][a_ch[a] * KCH] = ra[a];
+    // split the 16 complex values: parity i & 1, k = 8 q + i / 2
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+#pragma unroll
+      for (int comp = 0; comp < 2; ++comp) {
+        u16 h[8], l[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) split_bf16(comp ? rb[2 * e + par].y : rb[2 * e + par].x, &h[e], &l[e]);
+        *(uint4*)&Bs[0][par][2 * fi + comp][8 * q] =
+            make_uint4(pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7]));
+        *(uint4*)&Bs[1][par][2 * fi + comp][8 * q] =
+            make_uint4(pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7]));
+      }
+    }
+    __syncthreads();
+    if (kc + 1 < nk) fetch(kc + 1);
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      uint4 ah[IM], al[IM], bh[IN], bl[IN];
+      const int kq = 8 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < IM; ++i) {
+        const int r = wr * WM + i * 16 + (lane & 15);
+        ah[i] = *(const uint4*)&As[0][par][r][kq];
+        al[i] = *(const uint4*)&As[1][par][r][kq];
+      }
+#pragma unroll
+      for (int j = 0; j < IN; ++j) {
+        const int c = wc * WN + j * 16 + (lane & 15);
+        bh[j] = *(const uint4*)&Bs[0][par][c][kq];
+        bl[j] = *(const uint4*)&Bs[1][par][c][kq];
+      }
+#pragma unroll
+      for (int i = 0; i < IM; ++i)
+#pragma unroll
+        for (int j = 0; j < IN; ++j) {
+          acc[par][i][j] = mfma_bf16(al[i], bh[j], acc[par][i][j]);
+          acc[par][i][j] = mfma_bf16(ah[i], bl[j], acc[par][i][j]);
+          acc[par][i][j] = mfma_bf16(ah[i], bh[j], acc[par][i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+  const int64_t rowlen = 2 * (int64_t)p.Fp;
+#pragma unroll
+  for (int i = 0; i < IM; ++i) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = it.t0 + wr * WM + i * 16 + 4 * (lane >> 4) + e;
+      if (row >= mi.L) continue;
+      const RingInfo rn = p.rings[mi.first_ring + row];
+      float* dn = four + (rn.frow + m) * rowlen;
+      float* ds = four + (p.rings[rn.mirror].frow + m) * rowlen;
+#pragma unroll
+      for (int j = 0; j < IN; ++j) {
+        const int col = it.c0 + wc * WN + j * 16 + (lane & 15);
+        if (col < twoF) {
+          const float S = acc[0][i][j][e];
+          const float A = acc[1][i][j][e];
+          dn[col] = S + A;
+          ds[col] = S - A;
+        }
+      }
+    }
+  }
+}
+
+// Analysis in BF16 split precision: out^T[c][k] = sum_j X^T[c][j] T[j][k]
+// with K = rings.  Both operands need the rings contiguous per lane, so the
+// Fourier rows are gathered 8 rings at a time per column and the table
+// chunks ([ring][8 k]) are transposed 8 x 8 in registers.
+template <int BC, int BK>
+__global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(DevPlan p, const WorkItem* items,
+                                                                     int64_t plane,
+                                                                     const float* __restrict__ four,
+                                                                     float* __restrict__ spec) {
+  constexpr int KJ = 32;
+  constexpr int WC = BC / 2, WK = BK / 2;
+  constexpr int IC = WC / 16, IK = WK / 16;
+  constexpr int NCH = BK / KCH;
+  static_assert(2 * (BC / 4) * (KJ / 8) == 256, "X units");
+  constexpr int TUNITS = 2 * NCH * (KJ / 8) * 2;  // (plane, parity, chunk, ring octet)
+  static_assert(TUNITS <= 256, "table units");
+  __shared__ __align__(16) u16 Xs[2][2][BC][KJ + BPAD];  // [plane][parity][col c][ring]
+  __shared__ __align__(16) u16 Ts[2][2][BK][KJ + BPAD];  // [plane][parity][k][ring]
+
+  const WorkItem it = items[blockIdx.x];
+  const MInfo mi = p.ms[it.m];
+  const int m = mi.m;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const u16* tab = (const u16*)p.tab;
+  const int twoF = 2 * p.F;
+  const int64_t rowlen = 2 * (int64_t)p.Fp;
+  const int nj = (mi.L + KJ - 1) / KJ;
+
+  // X unit: (parity, column quad, ring octet)
+  const int x_oct = tid % (KJ / 8);
+  const int x_cq = (tid / (KJ / 8)) % (BC / 4);
+  const int x_par = tid / ((KJ / 8) * (BC / 4));
+  const int x_c = it.c0 + 4 * x_cq;
+  // table unit: (plane, parity, chunk, ring octet)
+  const int t_oct = tid % (KJ / 8);
+  const int t_ch = (tid / (KJ / 8)) % NCH;
+  const int t_par = (tid / ((KJ / 8) * NCH)) % 2;
+  const int t_pl = tid / ((KJ / 8) * NCH * 2);
+  const int t_kch = it.t0 / KCH + t_ch;
+  const bool t_ok = tid < TUNITS && t_kch * KCH < (t_par ? mi.Kp[1] : mi.Kp[0]);
+  const int64_t t_base = (t_pl ? plane : 0) + (t_par ? mi.toff[1] : mi.toff[0]) + (int64_t)t_kch * mi.Lp * KCH;
+
+  float4 rx[8];
+  uint4 rt[8];
+  auto fetch = [&](int jc) {
+    const int r0 = jc * KJ + 8 * x_oct;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = r0 + e;
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (r < mi.L && x_c < 2 * p.Fp) {
+        const int64_t fr = p.rings[mi.first_ring + r].frow;
+        v = *(const float4*)(four + ((fr + m) * 2 + x_par) * rowlen + x_c);
+      }
+      rx[e] = v;
+    }
+    const int t0 = jc * KJ + 8 * t_oct;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = t0 + e;
+      rt[e] = (t_ok && r < mi.Lp) ? *(const uint4*)(tab + t_base + (int64_t)r * KCH) : make_uint4(0, 0, 0, 0);
+    }
+  };
+
+  f32x4 acc[2][IC][IK];
+#pragma unroll
+  for (int par = 0; par < 2; ++par)
+#pragma unroll
+    for (int i = 0; i < IC; ++i)
+#pragma unroll
+      for (int j = 0; j < IK; ++j) acc[par][i][j] = f32x4{0, 0, 0, 0};
+
+  fetch(0);
+  for (int jc = 0; jc < nj; ++jc) {
+    // X: 4 columns x 8 rings -> per column 8 rings of hi and lo
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      u16 h[8], l[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float v = cc == 0 ? rx[e].x : cc == 1 ? rx[e].y : cc == 2 ? rx[e].z : rx[e].w;
+        split_bf16(v, &h[e], &l[e]);
+      }
+      *(uint4*)&Xs[0][x_par][4 * x_cq + cc][8 * x_oct] =
+          make_uint4(pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7]));
+      *(uint4*)&Xs[1][x_par][4 * x_cq + cc][8 * x_oct] =
+          make_uint4(pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7]));
+    }
+    // table: 8 rings x 8 k (16-bit) -> 8 k x 8 rings
+    {
+      const uint32_t* w = (const uint32_t*)rt;  // w[4 e + d] holds k = 2d, 2d + 1 of ring e
+#pragma unroll
+      for (int kk = 0; kk < KCH; ++kk) {
+        uint32_t o[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const uint32_t a = w[4 * (2 * d) + (kk >> 1)];
+          const uint32_t b = w[4 * (2 * d + 1) + (kk >> 1)];
+          o[d] = (kk & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+        }
+        if (tid < TUNITS) *(uint4*)&Ts[t_pl][t_par][t_ch * KCH + kk][8 * t_oct] = make_uint4(o[0], o[1], o[2], o[3]);
+      }
+    }
+    __syncthreads();
+    if (jc + 1 < nj) fetch(jc + 1);
+#pragma unroll
+    for (int par = 0; par < 2; ++par) {
+      uint4 ah[IC], al[IC], bh[IK], bl[IK];
+      const int jq = 8 * (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < IC; ++i) {
+        const int c = wr * WC + i * 16 + (lane & 15);
+        ah[i] = *(const uint4*)&Xs[0][par][c][jq];
+        al[i] = *(const uint4*)&Xs[1][par][c][jq];
+      }
+#pragma unroll
+      for (int j = 0; j < IK; ++j) {
+        const int k = wc * WK + j * 16 + (lane & 15);
+        bh[j] = *(const uint4*)&Ts[0][par][k][jq];
+        bl[j] = *(const uint4*)&Ts[1][par][k][jq];
+      }
+#pragma unroll
+      for (int i = 0; i < IC; ++i)
+#pragma unroll
+        for (int j = 0; j < IK; ++j) {
+          acc[par][i][j] = mfma_bf16(al[i], bh[j], acc[par][i][j]);
+          acc[par][i][j] = mfma_bf16(ah[i], bl[j], acc[par][i][j]);
+          acc[par][i][j] = mfma_bf16(ah[i], bh[j], acc[par][i][j]);
+        }
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int par = 0; par < 2; ++par) {
+    const int K = par ? mi.K[1] : mi.K[0];
+#pragma unroll
+    for (int j = 0; j < IK; ++j) {
+      const int k = it.t0 + wc * WK + j * 16 + (lane & 15);
+      if (k >= K) continue;
+      float2* dst = (float2*)spec + (mi.spec_off + 2 * k + par);
+#pragma unroll
+      for (int i = 0; i < IC; ++i) {
+#pragma unroll
+        for (int e = 0; e < 4; e += 2) {
+          const int c = it.c0 + wr * WC + i * 16 + 4 * (lane >> 4) + e;
+          if (c < twoF) {
+            float2 v = make_float2(acc[par][i][j][e], acc[par][i][j][e + 1]);
+            if (m == 0) v.y = 0.f;
+            dst[(int64_t)(c >> 1) * p.nspec] = v;
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Tile shapes and launchers
 // ---------------------------------------------------------------------------
 
 constexpr int INV64_BM = 64, INV64_BN = 64, INV64_KI = 16, DIR64_BC = 64, DIR64_BK = 64, DIR64_KJ = 16;
 constexpr int INV32_BM = 128, INV32_BN = 128, INV32_KI = 16, DIR32_BC = 128, DIR32_BK = 64, DIR32_KJ = 16;
+constexpr int INVB_BM = 128, INVB_BN = 128, DIRB_BC = 128, DIRB_BK = 64;
 
 void legendre_tiles(int prec, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols) {
   if (prec == SHT_FP64) {
@@ -394,15 +737,20 @@ void legendre_tiles(int prec, int* inv_rows, int* inv_cols, int* dir_rows, int* 
     *inv_cols = INV64_BN;
     *dir_rows = DIR64_BK;
     *dir_cols = DIR64_BC;
-  } else {
+  } else if (prec == SHT_FP32) {
     *inv_rows = INV32_BM;
     *inv_cols = INV32_BN;
     *dir_rows = DIR32_BK;
     *dir_cols = DIR32_BC;
+  } else {
+    *inv_rows = INVB_BM;
+    *inv_cols = INVB_BN;
+    *dir_rows = DIRB_BK;
+    *dir_cols = DIRB_BC;
   }
 }
 
-hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* items, int nitems,
+hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
                                    const void* spec, void* four, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (prec == SHT_FP64)
@@ -412,11 +760,12 @@ hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* i
     hipLaunchKernelGGL((legendre_inverse_kernel<float, INV32_BM, INV32_BN, INV32_KI>), dim3(nitems), dim3(256), 0, s, p,
                        items, (const float*)spec, (float*)four);
   else
-    return hipErrorNotSupported;
+    hipLaunchKernelGGL((legendre_inverse_bf16x3_kernel<INVB_BM, INVB_BN>), dim3(nitems), dim3(256), 0, s, p, items,
+                       plane, (const float*)spec, (float*)four);
   return hipGetLastError();
 }
 
-hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* items, int nitems,
+hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
                                   const void* four, void* spec, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (prec == SHT_FP64)
@@ -426,7 +775,8 @@ hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* it
     hipLaunchKernelGGL((legendre_direct_kernel<float, DIR32_BC, DIR32_BK, DIR32_KJ>), dim3(nitems), dim3(256), 0, s, p,
                        items, (const float*)four, (float*)spec);
   else
-    return hipErrorNotSupported;
+    hipLaunchKernelGGL((legendre_direct_bf16x3_kernel<DIRB_BC, DIRB_BK>), dim3(nitems), dim3(256), 0, s, p, items, plane,
+                       (const float*)four, (float*)spec);
   return hipGetLastError();
 }
 

@@ -106,9 +106,10 @@ hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& m
                                       double* out, hipStream_t s);
 
 // legendre.hip
-hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* items, int nitems,
+// plane: element offset of the lo plane of a BF16 split table (unused otherwise)
+hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
                                    const void* spec, void* four, hipStream_t s);
-hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* items, int nitems,
+hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
                                   const void* four, void* spec, hipStream_t s);
 // tile shapes the work lists are built for
 void legendre_tiles(int prec, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols);

@@ -16,6 +16,7 @@ CASES = [
     (79, "full", 17, "fp32"),
     (31, "octahedral", 3, "fp64"),
     (47, "octahedral", 33, "fp32"),
+    (47, "octahedral", 33, "bf16x3"),
 ]
 
 

@@ -66,7 +66,7 @@ def _first_ring(geo, m):
 
 
 @pytest.mark.parametrize("N,grid,prec", [(79, "full", "fp64"), (63, "octahedral", "fp64"), (63, "octahedral", "fp32"),
-                                         (1279, "octahedral", "fp64")])
+                                         (63, "octahedral", "bf16x3"), (1279, "octahedral", "fp64")])
 def test_pbar_tables(sht, N, grid, prec):
     with sht.Plan(N, grid, 1, prec) as plan:
         geo = oracle.grid_geometry(N, grid)
@@ -86,6 +86,10 @@ def test_pbar_tables(sht, N, grid, prec):
                        + 2 * (m + n) * 2.2e-16 * np.abs(ref))
             if prec == "fp64":
                 _check_le(np.abs(tab - ref), bound64, f"m={m}")
+            elif prec == "bf16x3":
+                # hi + lo keeps 16 significant bits of the float32 value
+                r32 = ref.astype(np.float32).astype(np.float64)
+                _check_le(np.abs(tab - r32), 2.0 ** -16 * np.abs(r32) + 1e-45 + bound64, f"m={m}")
             else:
                 ulp = np.spacing(np.abs(ref.astype(np.float32))).astype(np.float64)
                 r32 = ref.astype(np.float32).astype(np.float64)

@@ -22,6 +22,9 @@ CASES = [
     (63, "octahedral", 33, "fp32"),
     (95, "octahedral", 130, "fp32"),
     (159, "octahedral", 5, "fp64"),
+    (79, "full", 3, "bf16x3"),
+    (63, "octahedral", 33, "bf16x3"),
+    (95, "octahedral", 130, "bf16x3"),
 ]
 
 
@@ -61,7 +64,7 @@ def test_direct_matches_oracle(sht, case):
 
 
 @pytest.mark.parametrize("case", [(79, "full", 1, "fp64"), (79, "full", 3, "fp32"), (63, "octahedral", 4, "fp64"),
-                                  (63, "octahedral", 4, "fp32")], ids=_ids)
+                                  (63, "octahedral", 4, "fp32"), (63, "octahedral", 4, "bf16x3")], ids=_ids)
 def test_round_trip(sht, case):
     N, grid, F, prec = case
     with sht.Plan(N, grid, F, prec) as plan:
@@ -69,7 +72,7 @@ def test_round_trip(sht, case):
         back = spec_to_complex(plan.direct(plan.inverse(spec_t)))
         spec_c = spec_c.copy()
         spec_c[:, : N + 1] = spec_c[:, : N + 1].real
-        tol = {"fp64": 1e-12, "fp32": 1e-5}[prec]
+        tol = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-5}[prec]
         assert rel_l2(back, spec_c) <= tol
 
 
@@ -82,7 +85,7 @@ def test_im_a0_ignored(sht):
         assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_deterministic(sht, prec):
     with sht.Plan(63, "octahedral", 19, prec) as plan:
         spec_t, _c = spec_inputs(plan, seed=6)
