@@ -136,6 +136,15 @@ def stage_report(N, geo, F, precision, per_stage_ms):
     return stages, roof
 
 
+def committed_traffic(workload, precision, stage):
+    """HBM bytes per launch of ``stage`` from the PMC summary committed under
+    profiles/ (FETCH_SIZE + WRITE_SIZE scaled by a copy of known size), or
+    None if there is none or the kernels changed since it was taken."""
+    from paper_1908_06096_amd.profiling import measured_traffic
+
+    return measured_traffic(os.path.join(HERE, "profiles", f"traffic_{workload}_{precision}.json"), stage)
+
+
 def run_gpu(workload, precision, steps, warmup, seed=0):
     import torch
 
@@ -295,6 +304,8 @@ def main():
     ap.add_argument("--variants", default="bf16x3,fp64",
                     help="comma-separated other precisions to time on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of this many MiB first (reference for PMC byte counters)")
     ap.add_argument("--no-oracle-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -302,10 +313,22 @@ def main():
               "(no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {args.copy_calibration} MiB")
+        del a, b
     res = run_gpu(args.workload, args.precision, args.steps, args.warmup)
     N, F = res["N"], res["F"]
     geo = geometry_counts(N, res["grid"])
     stages, roof = stage_report(N, geo, F, args.precision, res["per_stage_ms"])
+    roof["traffic"] = committed_traffic(args.workload, args.precision, roof["kernel"])
 
     ms_per_step = res["total_ms"] / args.steps
     value = 2.0 * F * args.steps / (res["total_ms"] * 1e-3)

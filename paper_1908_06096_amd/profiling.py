@@ -1,0 +1,135 @@
+"""Summaries of rocprofv3 output for this library's kernels.
+
+    python -m paper_1908_06096_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_1908_06096_amd.profiling traffic <fetch_counter_collection.csv> \
+        <write_counter_collection.csv> <copy_bytes> <out.json> "<commands>"
+
+``stats`` turns a ``--kernel-trace --stats`` summary into a short markdown
+table.  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+runs into HBM bytes per dispatch for each kernel, scaled by what the same
+counters read for a plain device copy of ``copy_bytes`` bytes captured in the
+same runs (the largest ``direct_copy_kernel`` dispatch), and records a hash
+of the kernel sources so that a figure is only reported while the kernels are
+unchanged.
+"""
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SOURCES = ["csrc/legendre.hip", "csrc/fft.hip", "csrc/sht_internal.h"]
+STAGE_KERNELS = {
+    "legendre_inverse": "legendre_inverse",
+    "fourier_synthesis": "fourier_synthesis_kernel",
+    "fourier_analysis": "fourier_analysis_kernel",
+    "legendre_direct": "legendre_direct",
+}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("shtmi::", "")
+
+
+def stats_markdown(csv_path, out_md, command):
+    rows = list(csv.DictReader(open(csv_path)))
+    lines = [
+        "# Kernel trace summary",
+        "",
+        "Command:",
+        "",
+        "```",
+        command,
+        "```",
+        "",
+        "| kernel | calls | total ms | average ms | % of GPU time |",
+        "|---|---|---|---|---|",
+    ]
+    for r in rows:
+        lines.append("| `%s` | %s | %.3f | %.3f | %.2f |" % (
+            _short(r["Name"]), r["Calls"], float(r["TotalDurationNs"]) / 1e6, float(r["AverageNs"]) / 1e6,
+            float(r["Percentage"])))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _per_dispatch(csv_path, counter):
+    vals = defaultdict(list)
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] == counter:
+            vals[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return vals
+
+
+def traffic_json(fetch_csv, write_csv, copy_bytes, out_json, commands):
+    fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _per_dispatch(write_csv, "WRITE_SIZE")
+
+    def copy_reading(vals):
+        cands = [max(v) for k, v in vals.items() if "direct_copy_kernel" in k]
+        return max(cands) if cands else None
+
+    cf, cw = copy_reading(fetch), copy_reading(write)
+    if not cf or not cw:
+        raise SystemExit("no copy-kernel dispatch found for calibration")
+    # KiB reading -> bytes: the copy moved copy_bytes in and copy_bytes out
+    scale_f = copy_bytes / cf
+    scale_w = copy_bytes / cw
+    kernels = {}
+    for stage, key in STAGE_KERNELS.items():
+        fk = [k for k in fetch if key in k and "shtmi" in k]
+        wk = [k for k in write if key in k and "shtmi" in k]
+        if not fk or not wk:
+            continue
+        f = sum(fetch[fk[0]]) / len(fetch[fk[0]])
+        w = sum(write[wk[0]]) / len(write[wk[0]])
+        kernels[stage] = {"kernel": _short(fk[0]), "fetch_bytes": f * scale_f, "write_bytes": w * scale_w,
+                          "fetch_kib_raw": f, "write_kib_raw": w}
+    out = {
+        "source_sha256": source_hash(),
+        "copy_bytes": copy_bytes,
+        "copy_fetch_kib": cf,
+        "copy_write_kib": cw,
+        "scale_fetch_bytes_per_kib": scale_f,
+        "scale_write_bytes_per_kib": scale_w,
+        "commands": commands,
+        "kernels": kernels,
+    }
+    with open(out_json, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+
+
+def measured_traffic(path, stage):
+    """HBM bytes per dispatch of ``stage`` from a committed traffic file, or
+    None when the file is absent or the kernel sources changed since."""
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(stage)
+    if not k:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "traffic":
+        traffic_json(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6])
+    else:
+        raise SystemExit(__doc__)
