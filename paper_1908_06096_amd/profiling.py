@@ -8,7 +8,8 @@
 table.  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
 runs into HBM bytes per dispatch for each kernel, scaled by what the same
 counters read for a plain device copy of ``copy_bytes`` bytes captured in the
-same runs (the largest ``direct_copy_kernel`` dispatch), and records a hash
+same runs (the runtime's ``copyBuffer`` dispatch whose write counter is the
+largest), and records a hash
 of the kernel sources so that a figure is only reported while the kernels are
 unchanged.
 """
@@ -76,11 +77,18 @@ def traffic_json(fetch_csv, write_csv, copy_bytes, out_json, commands):
     fetch = _per_dispatch(fetch_csv, "FETCH_SIZE")
     write = _per_dispatch(write_csv, "WRITE_SIZE")
 
-    def copy_reading(vals):
-        cands = [max(v) for k, v in vals.items() if "direct_copy_kernel" in k]
-        return max(cands) if cands else None
+    def copy_dispatch(path, counter):
+        best = None
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"]:
+                v = float(r["Counter_Value"])
+                if best is None or v > best[1]:
+                    best = (r["Dispatch_Id"], v)
+        return best
 
-    cf, cw = copy_reading(fetch), copy_reading(write)
+    wd = copy_dispatch(write_csv, "WRITE_SIZE")
+    fd = copy_dispatch(fetch_csv, "FETCH_SIZE")
+    cf, cw = (fd[1] if fd else None), (wd[1] if wd else None)
     if not cf or not cw:
         raise SystemExit("no copy-kernel dispatch found for calibration")
     # KiB reading -> bytes: the copy moved copy_bytes in and copy_bytes out
