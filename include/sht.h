@@ -113,8 +113,22 @@ typedef struct sht_info {
   int64_t table_bytes;   /* resident Pbar tables */
   int64_t plan_bytes;    /* every device byte the plan holds */
   int32_t elem_bytes;    /* 8 for SHT_FP64, 4 otherwise */
-  int32_t reserved;
+  int32_t tile;          /* Legendre column-tile variant in use (enum sht_tile) */
 } sht_info;
+
+/* Column-tile variants of the Legendre products: the 2F real columns of a
+ * product are cut into tiles of 128, 64 or 32 columns.  Plans start with the
+ * narrowest tile that covers 2F (FP64: 64 or 32; BF16X3: 128 only). */
+enum sht_tile { SHT_TILE_C128 = 0, SHT_TILE_C64 = 1, SHT_TILE_C32 = 2 };
+
+typedef struct sht_batch_s* sht_batch_t;
+
+/* Batch flags. */
+enum sht_batch_flags {
+  SHT_BATCH_PERSISTENT = 1, /* each stage's launch uses only as many work groups as stay resident,
+                               each looping over the concatenated work list */
+  SHT_BATCH_GRAPH = 2       /* capture the stage launches in a HIP graph on first use, replay after */
+};
 
 /* Create a plan: geometry, Gaussian latitudes and weights (Newton iteration
  * on P_nlat in float64), Pbar_n^m tables (float64 recurrence, rounded once
@@ -184,6 +198,54 @@ int sht_fourier_analysis(sht_plan_t plan, const void* grid, void* fourier,
  * (n - m odd) summed over the north rings carrying m. */
 int sht_legendre_direct(sht_plan_t plan, const void* fourier, void* spec,
                         void* hip_stream);
+
+/* Switch a plan's Legendre products to another column-tile variant (results
+ * are unchanged: every output keeps its summation order).  Synchronises
+ * `hip_stream`.  SHT_EINVAL if the variant is not available for the plan's
+ * precision. */
+int sht_plan_set_tile(sht_plan_t plan, int tile, void* hip_stream);
+
+/* Batches: many independent transforms of uneven truncation and field count
+ * run in shared launches -- one launch per stage (per tile variant present
+ * for the Legendre products) over the concatenation of every plan's work
+ * list, ordered by cost, largest first.  This is the report's batching of
+ * the Legendre products across the second spherical dimension (section
+ * 4.2.4) taken one step further: across transforms, with each product at
+ * its own size instead of zero-padding to a common one, and its wish for an
+ * FFT batched over differing sizes (section 4.2.5) for all rings of all
+ * transforms at once.
+ *
+ * All plans must have the same precision and outlive the batch.  The batch
+ * owns only its work lists and descriptor tables. */
+int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags, void* hip_stream);
+
+/* Workspace bytes for the whole batch (the plans' workspaces, 256-byte
+ * aligned, back to back). */
+size_t sht_batch_workspace_size(sht_batch_t batch);
+
+/* Bind the device buffers of every transform: spec[i] and grid[i] in plan
+ * i's layouts, one workspace of sht_batch_workspace_size bytes.  Copies a
+ * small descriptor table to the device (synchronous).  Rebinding is allowed
+ * between runs; a captured graph reads the table, so it stays valid. */
+int sht_batch_bind(sht_batch_t batch, void* const* spec, void* const* grid, void* workspace);
+
+/* Synthesis / analysis of every transform of the batch on `hip_stream`
+ * (asynchronous).  SHT_EINVAL before the first sht_batch_bind. */
+int sht_batch_inverse(sht_batch_t batch, void* hip_stream);
+int sht_batch_direct(sht_batch_t batch, void* hip_stream);
+
+/* Autotuner: for each distinct (truncation, grid, fields) of the batch, time
+ * the two Legendre products with every tile variant available and keep the
+ * fastest; rebuilds the work lists (and drops a captured graph).  Reads the
+ * bound spectral inputs, uses the bound workspace as scratch and a
+ * temporary array for analysis output: bound inputs and outputs are left as
+ * they were.  Allocates temporaries; synchronises `hip_stream`. */
+int sht_batch_tune(sht_batch_t batch, void* hip_stream);
+
+/* The tile variant chosen for each plan of the batch (n entries). */
+int sht_batch_tiles(sht_batch_t batch, int32_t* out);
+
+int sht_batch_destroy(sht_batch_t batch);
 
 /* Human-readable text of a status code. */
 const char* sht_strerror(int status);

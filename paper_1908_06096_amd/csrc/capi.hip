@@ -1,11 +1,15 @@
 // Host runtime and C ABI: plan construction (geometry, FFT classes, table
-// layout, work lists), one device arena per plan, and the stream-ordered
-// entry points.  Following the report's restructured time step (section
-// 4.2.3), everything that allocates or copies metadata happens once at plan
-// creation; the transform calls only enqueue kernels.
+// layout, work lists), one device arena per plan, the stream-ordered entry
+// points, and batches of plans run in shared launches.  Following the
+// report's restructured time step (section 4.2.3), everything that allocates
+// or copies metadata happens once at plan (or batch) creation; the transform
+// calls only enqueue kernels.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <numeric>
 #include <vector>
 
 #include "sht_internal.h"
@@ -69,18 +73,51 @@ bool fits_registers(int L, const std::vector<int>& rad) {
   return true;
 }
 
+// The dynamic-LDS limit is a property of the kernel functions: raise it to
+// the largest any plan needs.
+std::mutex g_lds_mu;
+size_t g_lds_max = 0;
+
+hipError_t ensure_lds(size_t bytes) {
+  std::lock_guard<std::mutex> lk(g_lds_mu);
+  if (bytes <= g_lds_max) return hipSuccess;
+  hipError_t e = fft_set_max_lds(bytes);
+  if (e == hipSuccess) g_lds_max = bytes;
+  return e;
+}
+
+int cu_count() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) return 256;
+  return n;
+}
+
+// Default column-tile variant for 2F real columns: the narrowest tile that
+// covers them (wider tiles only waste MFMA work on padding columns).
+int default_variant(int prec, int F) {
+  const int cols = 2 * F;
+  if (prec == SHT_BF16X3) return TILE_C128;
+  if (cols <= 32) return TILE_C32;
+  if (cols <= 64 || prec == SHT_FP64) return TILE_C64;
+  return TILE_C128;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
 }  // namespace
 
 struct sht_plan_s {
   int N = 0, grid = 0, F = 0, prec = 0, nlat = 0, nh = 0, Fp = 0;
   int64_t npts = 0, nspec = 0, nfour = 0;
   int elem = 8;
+  int variant = TILE_C128;
   std::vector<RingInfo> rings;
   std::vector<FftClass> classes;
   std::vector<MInfo> ms;
   std::vector<int64_t> ring_off, four_row;
   std::vector<WorkItem> inv_items, dir_items;
-  std::vector<int2> syn_items, ana_items;
+  std::vector<FftItem> syn_items, ana_items;
   int64_t tab_plane = 0;
   size_t tab_bytes = 0, fft_bytes = 0;
   size_t lds_syn = 0, lds_ana = 0;
@@ -89,15 +126,47 @@ struct sht_plan_s {
   void* arena = nullptr;
   size_t arena_bytes = 0;
   DevPlan dp{};
+  DevPlan* d_self = nullptr;
   WorkItem* d_inv = nullptr;
   WorkItem* d_dir = nullptr;
-  int2* d_syn = nullptr;
-  int2* d_ana = nullptr;
+  FftItem* d_syn = nullptr;
+  FftItem* d_ana = nullptr;
   MInfo* d_ms = nullptr;
   FftClass* d_cls = nullptr;
 };
 
 namespace {
+
+// Legendre work items of one plan for a tile variant, tagged with `plan`.
+void legendre_items(const sht_plan_s* p, int variant, int plan, std::vector<WorkItem>* inv,
+                    std::vector<WorkItem>* dir) {
+  int ir, ic, dr, dc;
+  legendre_tiles(p->prec, variant, &ir, &ic, &dr, &dc);
+  const int twoF = 2 * p->F;
+  for (const MInfo& mi : p->ms) {
+    if (mi.L == 0) continue;
+    for (int t0 = 0; t0 < mi.L; t0 += ir)
+      for (int c0 = 0; c0 < twoF; c0 += ic) inv->push_back(WorkItem{mi.m, t0, c0, plan});
+    const int kmax = std::max(mi.K[0], mi.K[1]);
+    for (int t0 = 0; t0 < kmax; t0 += dr)
+      for (int c0 = 0; c0 < twoF; c0 += dc) dir->push_back(WorkItem{mi.m, t0, c0, plan});
+  }
+}
+
+// FFT work items of one plan, longest transforms first.
+void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::vector<FftItem>* ana) {
+  std::vector<int> order(p->nlat);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return p->classes[p->rings[a].cls].L > p->classes[p->rings[b].cls].L;
+  });
+  const int fchunk = 16;
+  for (int j : order)
+    for (int f0 = 0; f0 < p->F; f0 += fchunk) {
+      syn->push_back(FftItem{j, f0, plan, 0});
+      if (j < p->nh) ana->push_back(FftItem{j, f0, plan, 0});
+    }
+}
 
 int build_host(sht_plan_s* p) {
   const int N = p->N;
@@ -204,45 +273,34 @@ int build_host(sht_plan_s* p) {
     p->ms.push_back(mi);
   }
   p->tab_plane = toff;
-  const int tab_elem = (p->prec == SHT_FP64) ? 8 : (p->prec == SHT_FP32 ? 4 : 4);
+  const int tab_elem = (p->prec == SHT_FP64) ? 8 : 4;  // BF16 split: two 2-byte planes
   p->tab_bytes = (size_t)toff * tab_elem;
 
   // ---- work lists (m ascending = cost descending for both products) ----
-  int ir, ic, dr, dc;
-  legendre_tiles(p->prec, &ir, &ic, &dr, &dc);
-  const int twoF = 2 * p->F;
-  for (const MInfo& mi : p->ms) {
-    if (mi.L == 0) continue;
-    for (int t0 = 0; t0 < mi.L; t0 += ir)
-      for (int c0 = 0; c0 < twoF; c0 += ic) p->inv_items.push_back(WorkItem{mi.m, t0, c0, 0});
-    const int kmax = std::max(mi.K[0], mi.K[1]);
-    for (int t0 = 0; t0 < kmax; t0 += dr)
-      for (int c0 = 0; c0 < twoF; c0 += dc) p->dir_items.push_back(WorkItem{mi.m, t0, c0, 0});
-  }
-  // FFT items, longest transforms first
-  std::vector<int> order(p->nlat);
-  for (int j = 0; j < p->nlat; ++j) order[j] = j;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return p->classes[p->rings[a].cls].L > p->classes[p->rings[b].cls].L;
-  });
-  const int fchunk = 16;
-  for (int j : order)
-    for (int f0 = 0; f0 < p->F; f0 += fchunk) {
-      p->syn_items.push_back(int2{j, f0});
-      if (j < p->nh) p->ana_items.push_back(int2{j, f0});
-    }
+  p->variant = default_variant(p->prec, p->F);
+  legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
+  fft_items(p, 0, &p->syn_items, &p->ana_items);
   return SHT_OK;
 }
-
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 int build_device(sht_plan_s* p, hipStream_t s) {
   struct Part {
     void** dst;
     size_t bytes;
   };
-  void *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft, *v_inv, *v_dir, *v_syn, *v_ana;
+  // the Legendre lists are sized for the largest list any variant needs, so
+  // that sht_plan_set_tile can switch variants in place
+  size_t inv_cap = p->inv_items.size(), dir_cap = p->dir_items.size();
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
+    if (!legendre_variant_supported(p->prec, v)) continue;
+    std::vector<WorkItem> a, b;
+    legendre_items(p, v, 0, &a, &b);
+    inv_cap = std::max(inv_cap, a.size());
+    dir_cap = std::max(dir_cap, b.size());
+  }
+  void *v_self, *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft, *v_inv, *v_dir, *v_syn, *v_ana;
   const Part parts[] = {
+      {&v_self, sizeof(DevPlan)},
       {&v_rings, sizeof(RingInfo) * p->rings.size()},
       {&v_cls, sizeof(FftClass) * p->classes.size()},
       {&v_ms, sizeof(MInfo) * p->ms.size()},
@@ -250,10 +308,10 @@ int build_device(sht_plan_s* p, hipStream_t s) {
       {&v_w, sizeof(double) * p->nlat},
       {&v_tab, p->tab_bytes},
       {&v_fft, p->fft_bytes},
-      {&v_inv, sizeof(WorkItem) * p->inv_items.size()},
-      {&v_dir, sizeof(WorkItem) * p->dir_items.size()},
-      {&v_syn, sizeof(int2) * p->syn_items.size()},
-      {&v_ana, sizeof(int2) * p->ana_items.size()},
+      {&v_inv, sizeof(WorkItem) * inv_cap},
+      {&v_dir, sizeof(WorkItem) * dir_cap},
+      {&v_syn, sizeof(FftItem) * p->syn_items.size()},
+      {&v_ana, sizeof(FftItem) * p->ana_items.size()},
   };
   size_t total = 0;
   for (const Part& q : parts) total += align256(q.bytes);
@@ -268,14 +326,6 @@ int build_device(sht_plan_s* p, hipStream_t s) {
     *q.dst = (char*)p->arena + o;
     o += align256(q.bytes);
   }
-  HIP_TRY(hipMemcpyAsync(v_rings, p->rings.data(), parts[0].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), parts[1].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_ms, p->ms.data(), parts[2].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_inv, p->inv_items.data(), parts[7].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_dir, p->dir_items.data(), parts[8].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_syn, p->syn_items.data(), parts[9].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_ana, p->ana_items.data(), parts[10].bytes, hipMemcpyHostToDevice, s));
-
   DevPlan& d = p->dp;
   d.N = p->N;
   d.nlat = p->nlat;
@@ -291,19 +341,226 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   d.w = (const double*)v_w;
   d.tab = v_tab;
   d.fft = v_fft;
+  d.tab_plane = p->tab_plane;
+  p->d_self = (DevPlan*)v_self;
   p->d_inv = (WorkItem*)v_inv;
   p->d_dir = (WorkItem*)v_dir;
-  p->d_syn = (int2*)v_syn;
-  p->d_ana = (int2*)v_ana;
+  p->d_syn = (FftItem*)v_syn;
+  p->d_ana = (FftItem*)v_ana;
   p->d_ms = (MInfo*)v_ms;
   p->d_cls = (FftClass*)v_cls;
+
+  HIP_TRY(hipMemcpyAsync(v_self, &p->dp, sizeof(DevPlan), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_rings, p->rings.data(), parts[1].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), parts[2].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_ms, p->ms.data(), parts[3].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_inv, p->inv_items.data(), sizeof(WorkItem) * p->inv_items.size(), hipMemcpyHostToDevice,
+                         s));
+  HIP_TRY(hipMemcpyAsync(v_dir, p->dir_items.data(), sizeof(WorkItem) * p->dir_items.size(), hipMemcpyHostToDevice,
+                         s));
+  HIP_TRY(hipMemcpyAsync(v_syn, p->syn_items.data(), parts[10].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_ana, p->ana_items.data(), parts[11].bytes, hipMemcpyHostToDevice, s));
 
   HIP_TRY(launch_gauss(p->nlat, (double*)v_mu, (double*)v_w, s));
   HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane, s));
   HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls, (int)p->classes.size(), p->classes.data(), v_fft, s));
-  HIP_TRY(fft_set_max_lds(std::max(p->lds_syn, p->lds_ana)));
+  HIP_TRY(ensure_lds(std::max(p->lds_syn, p->lds_ana)));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
+  return SHT_OK;
+}
+
+IoBind bind_of(const void* spec, const void* grid, const void* ws) {
+  return IoBind{const_cast<void*>(spec), const_cast<void*>(grid), const_cast<void*>(ws), nullptr};
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+struct sht_batch_s {
+  int n = 0, prec = 0, flags = 0;
+  std::vector<sht_plan_t> plans;
+  std::vector<int> variant;
+  std::vector<WorkItem> inv[NUM_TILE_VARIANTS], dir[NUM_TILE_VARIANTS];
+  std::vector<FftItem> syn, ana;
+  std::vector<size_t> ws_off;
+  size_t ws_bytes = 0;
+  size_t lds_syn = 0, lds_ana = 0;
+  std::vector<IoBind> io_host;
+  bool bound = false;
+  // device
+  void* arena = nullptr;
+  DevPlan* d_plans = nullptr;
+  IoBind* d_io = nullptr;
+  WorkItem* d_inv[NUM_TILE_VARIANTS] = {};
+  WorkItem* d_dir[NUM_TILE_VARIANTS] = {};
+  FftItem* d_syn = nullptr;
+  FftItem* d_ana = nullptr;
+  int grid_inv[NUM_TILE_VARIANTS] = {}, grid_dir[NUM_TILE_VARIANTS] = {};
+  int grid_syn = 0, grid_ana = 0;
+  hipGraphExec_t g_inv = nullptr, g_dir = nullptr;
+};
+
+namespace {
+
+// Cost model used to order a batch's items (largest first, so that the
+// grid-stride assignment ends with short items): K chunks of a synthesis
+// tile, rings of an analysis tile, transform length of an FFT item.
+int64_t inv_cost(const sht_batch_s* b, const WorkItem& w) {
+  const MInfo& mi = b->plans[w.plan]->ms[w.m];
+  return (int64_t)std::max(mi.Kp[0], mi.Kp[1]);
+}
+
+int64_t dir_cost(const sht_batch_s* b, const WorkItem& w) { return (int64_t)b->plans[w.plan]->ms[w.m].L; }
+
+int64_t fft_cost(const sht_batch_s* b, const FftItem& w) {
+  const sht_plan_s* p = b->plans[w.plan];
+  return (int64_t)p->classes[p->rings[w.ring].cls].L;
+}
+
+void destroy_graphs(sht_batch_s* b) {
+  if (b->g_inv) (void)hipGraphExecDestroy(b->g_inv);
+  if (b->g_dir) (void)hipGraphExecDestroy(b->g_dir);
+  b->g_inv = b->g_dir = nullptr;
+}
+
+// (Re)build the batch's work lists from the per-plan variants and upload them.
+int batch_upload(sht_batch_s* b, hipStream_t s) {
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
+    b->inv[v].clear();
+    b->dir[v].clear();
+  }
+  b->syn.clear();
+  b->ana.clear();
+  for (int i = 0; i < b->n; ++i) {
+    legendre_items(b->plans[i], b->variant[i], i, &b->inv[b->variant[i]], &b->dir[b->variant[i]]);
+    fft_items(b->plans[i], i, &b->syn, &b->ana);
+  }
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
+    std::stable_sort(b->inv[v].begin(), b->inv[v].end(),
+                     [&](const WorkItem& x, const WorkItem& y) { return inv_cost(b, x) > inv_cost(b, y); });
+    std::stable_sort(b->dir[v].begin(), b->dir[v].end(),
+                     [&](const WorkItem& x, const WorkItem& y) { return dir_cost(b, x) > dir_cost(b, y); });
+  }
+  std::stable_sort(b->syn.begin(), b->syn.end(),
+                   [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
+  std::stable_sort(b->ana.begin(), b->ana.end(),
+                   [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
+
+  destroy_graphs(b);
+  if (b->arena) {
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFree(b->arena));
+    b->arena = nullptr;
+  }
+  size_t total = align256(sizeof(DevPlan) * b->n) + align256(sizeof(IoBind) * b->n);
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v)
+    total += align256(sizeof(WorkItem) * b->inv[v].size()) + align256(sizeof(WorkItem) * b->dir[v].size());
+  total += align256(sizeof(FftItem) * b->syn.size()) + align256(sizeof(FftItem) * b->ana.size());
+  if (hipMalloc(&b->arena, total) != hipSuccess) {
+    (void)hipGetLastError();
+    b->arena = nullptr;
+    return SHT_ENOMEM;
+  }
+  char* o = (char*)b->arena;
+  auto take = [&](size_t bytes) {
+    char* r = o;
+    o += align256(bytes);
+    return (void*)r;
+  };
+  b->d_plans = (DevPlan*)take(sizeof(DevPlan) * b->n);
+  b->d_io = (IoBind*)take(sizeof(IoBind) * b->n);
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
+    b->d_inv[v] = (WorkItem*)take(sizeof(WorkItem) * b->inv[v].size());
+    b->d_dir[v] = (WorkItem*)take(sizeof(WorkItem) * b->dir[v].size());
+  }
+  b->d_syn = (FftItem*)take(sizeof(FftItem) * b->syn.size());
+  b->d_ana = (FftItem*)take(sizeof(FftItem) * b->ana.size());
+
+  std::vector<DevPlan> dps(b->n);
+  for (int i = 0; i < b->n; ++i) dps[i] = b->plans[i]->dp;
+  HIP_TRY(hipMemcpy(b->d_plans, dps.data(), sizeof(DevPlan) * b->n, hipMemcpyHostToDevice));
+  if (b->bound) HIP_TRY(hipMemcpy(b->d_io, b->io_host.data(), sizeof(IoBind) * b->n, hipMemcpyHostToDevice));
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
+    if (!b->inv[v].empty())
+      HIP_TRY(hipMemcpy(b->d_inv[v], b->inv[v].data(), sizeof(WorkItem) * b->inv[v].size(), hipMemcpyHostToDevice));
+    if (!b->dir[v].empty())
+      HIP_TRY(hipMemcpy(b->d_dir[v], b->dir[v].data(), sizeof(WorkItem) * b->dir[v].size(), hipMemcpyHostToDevice));
+  }
+  HIP_TRY(hipMemcpy(b->d_syn, b->syn.data(), sizeof(FftItem) * b->syn.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->d_ana, b->ana.data(), sizeof(FftItem) * b->ana.size(), hipMemcpyHostToDevice));
+
+  // grid sizes: persistent = as many work groups as can be resident
+  const bool persistent = b->flags & SHT_BATCH_PERSISTENT;
+  const int cus = cu_count();
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
+    const int ni = (int)b->inv[v].size(), nd = (int)b->dir[v].size();
+    b->grid_inv[v] = ni;
+    b->grid_dir[v] = nd;
+    if (persistent && ni) b->grid_inv[v] = std::min(ni, cus * legendre_blocks_per_cu(b->prec, v, true));
+    if (persistent && nd) b->grid_dir[v] = std::min(nd, cus * legendre_blocks_per_cu(b->prec, v, false));
+  }
+  const size_t vs = fft_grid_blocks((int)b->syn.size()), va = fft_grid_blocks((int)b->ana.size());
+  b->grid_syn = (int)vs;
+  b->grid_ana = (int)va;
+  if (persistent) {
+    // a multiple of 8 keeps each virtual block on the XCD its id selects
+    const int rs = std::max(8, cus * fft_blocks_per_cu(b->prec, b->lds_syn) / 8 * 8);
+    const int ra = std::max(8, cus * fft_blocks_per_cu(b->prec, b->lds_ana) / 8 * 8);
+    b->grid_syn = (int)std::min<size_t>(vs, rs);
+    b->grid_ana = (int)std::min<size_t>(va, ra);
+  }
+  return SHT_OK;
+}
+
+int batch_enqueue_inverse(sht_batch_s* b, hipStream_t s) {
+  const IoBind none{};
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v)
+    HIP_TRY(launch_legendre_inverse(b->d_plans, b->prec, v, b->d_inv[v], (int)b->inv[v].size(), b->d_io, none,
+                                    b->grid_inv[v], s));
+  HIP_TRY(launch_fourier_synthesis(b->d_plans, b->prec, b->d_syn, (int)b->syn.size(), b->d_io, none, b->lds_syn,
+                                   b->grid_syn, s));
+  return SHT_OK;
+}
+
+int batch_enqueue_direct(sht_batch_s* b, hipStream_t s) {
+  const IoBind none{};
+  HIP_TRY(launch_fourier_analysis(b->d_plans, b->prec, b->d_ana, (int)b->ana.size(), b->d_io, none, b->lds_ana,
+                                  b->grid_ana, s));
+  for (int v = 0; v < NUM_TILE_VARIANTS; ++v)
+    HIP_TRY(launch_legendre_direct(b->d_plans, b->prec, v, b->d_dir[v], (int)b->dir[v].size(), b->d_io, none,
+                                   b->grid_dir[v], s));
+  return SHT_OK;
+}
+
+// Run through a captured graph when the batch asks for one (not on the
+// legacy default stream, which cannot be captured).
+int batch_run(sht_batch_s* b, hipStream_t s, bool inverse) {
+  if (!b->bound) return SHT_EINVAL;
+  hipGraphExec_t* exec = inverse ? &b->g_inv : &b->g_dir;
+  if (!(b->flags & SHT_BATCH_GRAPH) || s == nullptr)
+    return inverse ? batch_enqueue_inverse(b, s) : batch_enqueue_direct(b, s);
+  if (!*exec) {
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = inverse ? batch_enqueue_inverse(b, s) : batch_enqueue_direct(b, s);
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc != SHT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      *exec = nullptr;
+      return hip_fail(e);
+    }
+  }
+  HIP_TRY(hipGraphLaunch(*exec, s));
   return SHT_OK;
 }
 
@@ -366,6 +623,7 @@ int sht_plan_info(sht_plan_t p, sht_info* out) {
   out->table_bytes = (int64_t)p->tab_bytes;
   out->plan_bytes = (int64_t)p->arena_bytes;
   out->elem_bytes = p->elem;
+  out->tile = p->variant;
   return SHT_OK;
 }
 
@@ -399,6 +657,19 @@ int sht_plan_legendre_table(sht_plan_t p, int m, double* out, int32_t* first_rin
   return SHT_OK;
 }
 
+int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
+  if (!p || !legendre_variant_supported(p->prec, tile)) return SHT_EINVAL;
+  std::vector<WorkItem> inv, dir;
+  legendre_items(p, tile, 0, &inv, &dir);
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  HIP_TRY(hipMemcpy(p->d_inv, inv.data(), sizeof(WorkItem) * inv.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p->d_dir, dir.data(), sizeof(WorkItem) * dir.size(), hipMemcpyHostToDevice));
+  p->inv_items = inv;
+  p->dir_items = dir;
+  p->variant = tile;
+  return SHT_OK;
+}
+
 size_t sht_workspace_size(sht_plan_t p) {
   if (!p) return 0;
   return (size_t)p->nfour * p->Fp * 2 * p->elem;
@@ -406,29 +677,31 @@ size_t sht_workspace_size(sht_plan_t p) {
 
 int sht_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* stream) {
   if (!p || !spec || !four) return SHT_EINVAL;
-  HIP_TRY(launch_legendre_inverse(p->dp, p->prec, p->d_inv, (int)p->inv_items.size(), p->tab_plane, spec, four,
-                                  (hipStream_t)stream));
+  HIP_TRY(launch_legendre_inverse(p->d_self, p->prec, p->variant, p->d_inv, (int)p->inv_items.size(), nullptr,
+                                  bind_of(spec, nullptr, four), (int)p->inv_items.size(), (hipStream_t)stream));
   return SHT_OK;
 }
 
 int sht_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream) {
   if (!p || !four || !grid) return SHT_EINVAL;
-  HIP_TRY(launch_fourier_synthesis(p->dp, p->prec, p->d_syn, (int)p->syn_items.size(), p->lds_syn, four, grid,
-                                   (hipStream_t)stream));
+  HIP_TRY(launch_fourier_synthesis(p->d_self, p->prec, p->d_syn, (int)p->syn_items.size(), nullptr,
+                                   bind_of(nullptr, grid, four), p->lds_syn,
+                                   (int)fft_grid_blocks((int)p->syn_items.size()), (hipStream_t)stream));
   return SHT_OK;
 }
 
 int sht_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* stream) {
   if (!p || !four || !grid) return SHT_EINVAL;
-  HIP_TRY(launch_fourier_analysis(p->dp, p->prec, p->d_ana, (int)p->ana_items.size(), p->lds_ana, grid, four,
-                                  (hipStream_t)stream));
+  HIP_TRY(launch_fourier_analysis(p->d_self, p->prec, p->d_ana, (int)p->ana_items.size(), nullptr,
+                                  bind_of(nullptr, grid, four), p->lds_ana,
+                                  (int)fft_grid_blocks((int)p->ana_items.size()), (hipStream_t)stream));
   return SHT_OK;
 }
 
 int sht_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream) {
   if (!p || !spec || !four) return SHT_EINVAL;
-  HIP_TRY(launch_legendre_direct(p->dp, p->prec, p->d_dir, (int)p->dir_items.size(), p->tab_plane, four, spec,
-                                 (hipStream_t)stream));
+  HIP_TRY(launch_legendre_direct(p->d_self, p->prec, p->variant, p->d_dir, (int)p->dir_items.size(), nullptr,
+                                 bind_of(spec, nullptr, four), (int)p->dir_items.size(), (hipStream_t)stream));
   return SHT_OK;
 }
 
@@ -444,6 +717,158 @@ int sht_direct(sht_plan_t p, const void* grid, void* spec, void* ws, void* strea
   int rc = sht_fourier_analysis(p, grid, ws, stream);
   if (rc != SHT_OK) return rc;
   return sht_legendre_direct(p, ws, spec, stream);
+}
+
+int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags, void* stream) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  if (!plans || n < 1 || (flags & ~(SHT_BATCH_PERSISTENT | SHT_BATCH_GRAPH))) return SHT_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!plans[i] || plans[i]->prec != plans[0]->prec) return SHT_EINVAL;
+  sht_batch_s* b = new (std::nothrow) sht_batch_s();
+  if (!b) return SHT_ENOMEM;
+  b->n = n;
+  b->prec = plans[0]->prec;
+  b->flags = flags;
+  b->plans.assign(plans, plans + n);
+  b->variant.resize(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    b->variant[i] = plans[i]->variant;
+    b->ws_off.push_back(off);
+    off += align256(sht_workspace_size(plans[i]));
+    b->lds_syn = std::max(b->lds_syn, plans[i]->lds_syn);
+    b->lds_ana = std::max(b->lds_ana, plans[i]->lds_ana);
+  }
+  b->ws_bytes = off;
+  const int rc = batch_upload(b, (hipStream_t)stream);
+  if (rc != SHT_OK) {
+    if (b->arena) (void)hipFree(b->arena);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return SHT_OK;
+}
+
+size_t sht_batch_workspace_size(sht_batch_t b) { return b ? b->ws_bytes : 0; }
+
+int sht_batch_bind(sht_batch_t b, void* const* spec, void* const* grid, void* workspace) {
+  if (!b || !spec || !grid || !workspace) return SHT_EINVAL;
+  std::vector<IoBind> io(b->n);
+  for (int i = 0; i < b->n; ++i) {
+    if (!spec[i] || !grid[i]) return SHT_EINVAL;
+    io[i] = IoBind{spec[i], grid[i], (char*)workspace + b->ws_off[i], nullptr};
+  }
+  HIP_TRY(hipMemcpy(b->d_io, io.data(), sizeof(IoBind) * b->n, hipMemcpyHostToDevice));
+  b->io_host = io;
+  b->bound = true;
+  return SHT_OK;
+}
+
+int sht_batch_inverse(sht_batch_t b, void* stream) {
+  if (!b) return SHT_EINVAL;
+  return batch_run(b, (hipStream_t)stream, true);
+}
+
+int sht_batch_direct(sht_batch_t b, void* stream) {
+  if (!b) return SHT_EINVAL;
+  return batch_run(b, (hipStream_t)stream, false);
+}
+
+int sht_batch_tune(sht_batch_t b, void* stream) {
+  if (!b || !b->bound) return SHT_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SHT_EHIP;
+  }
+  // one measurement per distinct (truncation, grid, fields) in the batch:
+  // the plan's two Legendre products with each supported tile variant (the
+  // second of two runs counts).  Synthesis reads the bound spectral input and
+  // writes the plan's workspace; analysis writes a temporary spectral array,
+  // so the caller's buffers keep their contents.
+  std::map<std::vector<int>, int> chosen;
+  int rc = SHT_OK;
+  for (int i = 0; i < b->n && rc == SHT_OK; ++i) {
+    sht_plan_s* p = b->plans[i];
+    const std::vector<int> key{p->N, p->grid, p->F};
+    auto hit = chosen.find(key);
+    if (hit != chosen.end()) {
+      b->variant[i] = hit->second;
+      continue;
+    }
+    int best = b->variant[i];
+    float best_ms = 1e30f;
+    for (int v = 0; v < NUM_TILE_VARIANTS && rc == SHT_OK; ++v) {
+      if (!legendre_variant_supported(b->prec, v)) continue;
+      std::vector<WorkItem> items, dir;
+      legendre_items(p, v, 0, &items, &dir);
+      const int ni = (int)items.size(), nd = (int)dir.size();
+      items.insert(items.end(), dir.begin(), dir.end());
+      WorkItem* d_items = nullptr;
+      void* d_spec = nullptr;
+      const size_t spec_bytes = (size_t)p->F * p->nspec * 2 * p->elem;
+      if (hipMalloc(&d_items, sizeof(WorkItem) * items.size()) != hipSuccess ||
+          hipMalloc(&d_spec, spec_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        if (d_items) (void)hipFree(d_items);
+        rc = SHT_ENOMEM;
+        break;
+      }
+      hipError_t e = hipMemcpy(d_items, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice);
+      const IoBind io = b->io_host[i];
+      const IoBind io_dir{d_spec, io.grid, io.ws, nullptr};
+      float ms = 0.f;
+      for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_legendre_inverse(p->d_self, p->prec, v, d_items, ni, nullptr, io, ni, s);
+        if (e == hipSuccess)
+          e = launch_legendre_direct(p->d_self, p->prec, v, d_items + ni, nd, nullptr, io_dir, nd, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      }
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      (void)hipFree(d_items);
+      (void)hipFree(d_spec);
+      if (e != hipSuccess) {
+        rc = hip_fail(e);
+        break;
+      }
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = v;
+      }
+    }
+    chosen[key] = best;
+    b->variant[i] = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SHT_OK) return rc;
+  return batch_upload(b, s);
+}
+
+int sht_batch_tiles(sht_batch_t b, int32_t* out) {
+  if (!b || !out) return SHT_EINVAL;
+  for (int i = 0; i < b->n; ++i) out[i] = b->variant[i];
+  return SHT_OK;
+}
+
+int sht_batch_destroy(sht_batch_t b) {
+  if (!b) return SHT_EINVAL;
+  int rc = SHT_OK;
+  destroy_graphs(b);
+  if (b->arena) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipFree(b->arena);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  delete b;
+  return rc;
 }
 
 const char* sht_strerror(int status) {

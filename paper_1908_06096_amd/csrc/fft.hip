@@ -261,8 +261,7 @@ constexpr int NUM_XCD = 8;
 // round-robin by id, so the FFT_FCHUNK fields of an item get ids that are
 // congruent modulo NUM_XCD and adjacent in dispatch order: they run on one
 // XCD at the same time and their strided accesses meet in that XCD's L2.
-__device__ inline bool decode_block(int nitems, int* item, int* slot) {
-  const int bid = blockIdx.x;
+__device__ inline bool decode_block(int bid, int nitems, int* item, int* slot) {
   const int grp = bid / (NUM_XCD * FFT_FCHUNK);
   const int r = bid - grp * (NUM_XCD * FFT_FCHUNK);
   *item = grp * NUM_XCD + r % NUM_XCD;
@@ -270,9 +269,11 @@ __device__ inline bool decode_block(int nitems, int* item, int* slot) {
   return *item < nitems;
 }
 
-size_t fft_grid_blocks(int nitems) {
+__host__ __device__ inline size_t fft_grid_blocks_dev(int nitems) {
   return (size_t)((nitems + NUM_XCD - 1) / NUM_XCD) * NUM_XCD * FFT_FCHUNK;
 }
+
+size_t fft_grid_blocks(int nitems) { return fft_grid_blocks_dev(nitems); }
 
 // ---------------------------------------------------------------------------
 // Synthesis: ring j, one field of the chunk [f0, f0 + FFT_FCHUNK).
@@ -282,17 +283,11 @@ size_t fft_grid_blocks(int nitems) {
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void fourier_synthesis_kernel(DevPlan p, const int2* items, int nitems,
-                                                                        const T* __restrict__ four,
-                                                                        T* __restrict__ grid) {
+__device__ __forceinline__ void synthesis_field(const DevPlan& p, int ring, int f, const T* __restrict__ four,
+                                                T* __restrict__ grid) {
   typedef typename V2T<T>::type C;
   extern __shared__ __align__(16) unsigned char smem[];
-  int item, slot;
-  if (!decode_block(nitems, &item, &slot)) return;
-  const int2 it = items[item];
-  const int f = it.y + slot;
-  if (f >= p.F) return;
-  const RingInfo ri = p.rings[it.x];
+  const RingInfo ri = p.rings[ring];
   const FftClass cl = p.classes[ri.cls];
   const int32_t* rad = p.classes[ri.cls].rad;
   const C* tabs = (const C*)p.fft;
@@ -338,17 +333,11 @@ __global__ __launch_bounds__(FFT_THREADS) void fourier_synthesis_kernel(DevPlan 
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void fourier_analysis_kernel(DevPlan p, const int2* items, int nitems,
-                                                                       const T* __restrict__ grid,
-                                                                       T* __restrict__ four) {
+__device__ __forceinline__ void analysis_field(const DevPlan& p, int ring, int f, const T* __restrict__ grid,
+                                               T* __restrict__ four) {
   typedef typename V2T<T>::type C;
   extern __shared__ __align__(16) unsigned char smem[];
-  int item, slot;
-  if (!decode_block(nitems, &item, &slot)) return;
-  const int2 it = items[item];
-  const int f = it.y + slot;
-  if (f >= p.F) return;
-  const RingInfo rn = p.rings[it.x];
+  const RingInfo rn = p.rings[ring];
   const RingInfo rs = p.rings[rn.mirror];
   const FftClass cl = p.classes[rn.cls];
   const int32_t* rad = p.classes[rn.cls].rad;
@@ -360,7 +349,7 @@ __global__ __launch_bounds__(FFT_THREADS) void fourier_analysis_kernel(DevPlan p
   C* fc = (C*)four;
   const int h = cl.h, mmax = rn.mmax, L = cl.L;
   const bool blue = cl.bluestein;
-  const T scale = (T)(p.w[it.x] / (double)rn.nlon);
+  const T scale = (T)(p.w[ring] / (double)rn.nlon);
   {
     for (int side = 0; side < 2; ++side) {
       const T* g = grid + (int64_t)f * p.npts + (side ? rs.goff : rn.goff);
@@ -404,28 +393,70 @@ size_t fft_lds_bytes(int prec, int L, int mmax) {
   return c * (padded + (mmax >= 0 ? (size_t)mmax + 1 : 0));
 }
 
-hipError_t launch_fourier_synthesis(const DevPlan& p, int prec, const int2* items, int nitems, size_t lds,
-                                    const void* four, void* grid, hipStream_t s) {
-  if (nitems == 0) return hipSuccess;
-  if (prec == SHT_FP64)
-    hipLaunchKernelGGL(fourier_synthesis_kernel<double>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
-                       items, nitems, (const double*)four, (double*)grid);
-  else
-    hipLaunchKernelGGL(fourier_synthesis_kernel<float>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
-                       items, nitems, (const float*)four, (float*)grid);
-  return hipGetLastError();
+// Kernels: work groups loop over virtual block ids (grid stride) so that a
+// launch of any size keeps the XCD grouping of decode_block.
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS) void fourier_synthesis_kernel(const DevPlan* __restrict__ plans,
+                                                                        const FftItem* __restrict__ items, int nitems,
+                                                                        const IoBind* __restrict__ io, IoBind io0) {
+  const int nvirt = (int)fft_grid_blocks_dev(nitems);
+  for (int v = blockIdx.x; v < nvirt; v += gridDim.x) {
+    int item, slot;
+    if (!decode_block(v, nitems, &item, &slot)) continue;
+    const FftItem it = items[item];
+    const DevPlan p = plans[it.plan];
+    const int f = it.f0 + slot;
+    if (f >= p.F) continue;
+    const IoBind b = io ? io[it.plan] : io0;
+    synthesis_field<T>(p, it.ring, f, (const T*)b.ws, (T*)b.grid);
+  }
 }
 
-hipError_t launch_fourier_analysis(const DevPlan& p, int prec, const int2* items, int nitems, size_t lds,
-                                   const void* grid, void* four, hipStream_t s) {
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS) void fourier_analysis_kernel(const DevPlan* __restrict__ plans,
+                                                                       const FftItem* __restrict__ items, int nitems,
+                                                                       const IoBind* __restrict__ io, IoBind io0) {
+  const int nvirt = (int)fft_grid_blocks_dev(nitems);
+  for (int v = blockIdx.x; v < nvirt; v += gridDim.x) {
+    int item, slot;
+    if (!decode_block(v, nitems, &item, &slot)) continue;
+    const FftItem it = items[item];
+    const DevPlan p = plans[it.plan];
+    const int f = it.f0 + slot;
+    if (f >= p.F) continue;
+    const IoBind b = io ? io[it.plan] : io0;
+    analysis_field<T>(p, it.ring, f, (const T*)b.grid, (T*)b.ws);
+  }
+}
+
+static hipError_t launch_fft(const void* f, int grid_blocks, size_t lds, hipStream_t s, const DevPlan* plans,
+                             const FftItem* items, int nitems, const IoBind* io, IoBind io0) {
+  void* args[] = {(void*)&plans, (void*)&items, (void*)&nitems, (void*)&io, (void*)&io0};
+  return hipLaunchKernel(f, dim3(grid_blocks), dim3(FFT_THREADS), args, lds, s);
+}
+
+hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+                                    const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  if (prec == SHT_FP64)
-    hipLaunchKernelGGL(fourier_analysis_kernel<double>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
-                       items, nitems, (const double*)grid, (double*)four);
-  else
-    hipLaunchKernelGGL(fourier_analysis_kernel<float>, dim3(fft_grid_blocks(nitems)), dim3(FFT_THREADS), lds, s, p,
-                       items, nitems, (const float*)grid, (float*)four);
-  return hipGetLastError();
+  const void* f = prec == SHT_FP64 ? (const void*)fourier_synthesis_kernel<double>
+                                   : (const void*)fourier_synthesis_kernel<float>;
+  return launch_fft(f, grid_blocks, lds, s, plans, items, nitems, io, io0);
+}
+
+hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+                                   const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  const void* f = prec == SHT_FP64 ? (const void*)fourier_analysis_kernel<double>
+                                   : (const void*)fourier_analysis_kernel<float>;
+  return launch_fft(f, grid_blocks, lds, s, plans, items, nitems, io, io0);
+}
+
+int fft_blocks_per_cu(int prec, size_t lds) {
+  int n = 0;
+  const void* f = prec == SHT_FP64 ? (const void*)fourier_synthesis_kernel<double>
+                                   : (const void*)fourier_synthesis_kernel<float>;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, FFT_THREADS, lds) != hipSuccess || n < 1) n = 1;
+  return n;
 }
 
 hipError_t fft_set_max_lds(size_t bytes) {

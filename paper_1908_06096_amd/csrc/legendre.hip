@@ -79,15 +79,15 @@ constexpr int LDS_PAD = 16;
 // while the current one is multiplied out of LDS.
 // ---------------------------------------------------------------------------
 
-template <typename T, int BM, int BN, int KI>
-__global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(DevPlan p, const WorkItem* items,
-                                                               const T* __restrict__ spec,
-                                                               T* __restrict__ four) {
+template <typename T, int BM, int BN, int KI, int WCOL>
+__device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it, const T* __restrict__ spec,
+                                             T* __restrict__ four) {
   typedef typename Acc<T>::type acc_t;
   typedef typename Vec<T>::type V;
   typedef typename Vec<T>::pair C2;
   constexpr int VN = Vec<T>::n;
-  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int WROW = 4 / WCOL;           // waves along rows x along columns
+  constexpr int WM = BM / WROW, WN = BN / WCOL;
   constexpr int IM = WM / 16, IN = WN / 16;
   constexpr int NC = KI / KCH;             // table chunks per parity per iteration
   constexpr int AUNITS = 2 * NC * BM;      // (parity, chunk, row) units of KCH elements
@@ -99,13 +99,12 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(DevPlan p, con
   __shared__ T As[2][KI][BM + LDS_PAD];
   __shared__ T Bs[2][KI][BN + LDS_PAD];
 
-  const WorkItem it = items[blockIdx.x];
   const MInfo mi = p.ms[it.m];
   const int m = mi.m;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WCOL, wc = wave % WCOL;
   const T* tab = (const T*)p.tab;
   const int twoF = 2 * p.F;
   const int kpmax = mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1];
@@ -229,15 +228,15 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(DevPlan p, con
 // operands fetched into registers during the multiply.
 // ---------------------------------------------------------------------------
 
-template <typename T, int BC, int BK, int KJ>
-__global__ __launch_bounds__(256, 2) void legendre_direct_kernel(DevPlan p, const WorkItem* items,
-                                                              const T* __restrict__ four,
-                                                              T* __restrict__ spec) {
+template <typename T, int BC, int BK, int KJ, int WKW>
+__device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it, const T* __restrict__ four,
+                                            T* __restrict__ spec) {
   typedef typename Acc<T>::type acc_t;
   typedef typename Vec<T>::type V;
   typedef typename Vec<T>::pair C2;
   constexpr int VN = Vec<T>::n;
-  constexpr int WC = BC / 2, WK = BK / 2;
+  constexpr int WCW = 4 / WKW;             // waves along columns c x along k
+  constexpr int WC = BC / WCW, WK = BK / WKW;
   constexpr int IC = WC / 16, IK = WK / 16;
   constexpr int CS = BC / VN;                 // vectors per X row segment
   constexpr int XUNITS = 2 * KJ * CS;
@@ -249,13 +248,12 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(DevPlan p, cons
   __shared__ T Xs[2][KJ][BC + LDS_PAD];
   __shared__ T Ts[2][KJ][BK + LDS_PAD];
 
-  const WorkItem it = items[blockIdx.x];
   const MInfo mi = p.ms[it.m];
   const int m = mi.m;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave / WKW, wc = wave % WKW;
   const T* tab = (const T*)p.tab;
   const int twoF = 2 * p.F;
   const int64_t rowlen = 2 * (int64_t)p.Fp;
@@ -416,10 +414,9 @@ __device__ inline uint32_t pack2(u16 a, u16 b) { return (uint32_t)a | ((uint32_t
 constexpr int BPAD = 8;
 
 template <int BM, int BN>
-__global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(DevPlan p, const WorkItem* items,
-                                                                      int64_t plane,
-                                                                      const float* __restrict__ spec,
-                                                                      float* __restrict__ four) {
+__device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const WorkItem it,
+                                                    const float* __restrict__ spec, float* __restrict__ four) {
+  const int64_t plane = p.tab_plane;
   constexpr int KI = 32;                  // k of each parity per iteration
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int IM = WM / 16, IN = WN / 16;
@@ -430,7 +427,6 @@ __global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(DevPlan p,
   __shared__ __align__(16) u16 As[2][2][BM][KI + BPAD];  // [plane][parity][row][k]
   __shared__ __align__(16) u16 Bs[2][2][BN][KI + BPAD];  // [plane][parity][col][k]
 
-  const WorkItem it = items[blockIdx.x];
   const MInfo mi = p.ms[it.m];
   const int m = mi.m;
   const int tid = threadIdx.x;
@@ -568,10 +564,9 @@ __global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(DevPlan p,
 // Fourier rows are gathered 8 rings at a time per column and the table
 // chunks ([ring][8 k]) are transposed 8 x 8 in registers.
 template <int BC, int BK>
-__global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(DevPlan p, const WorkItem* items,
-                                                                     int64_t plane,
-                                                                     const float* __restrict__ four,
-                                                                     float* __restrict__ spec) {
+__device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkItem it,
+                                                   const float* __restrict__ four, float* __restrict__ spec) {
+  const int64_t plane = p.tab_plane;
   constexpr int KJ = 32;
   constexpr int WC = BC / 2, WK = BK / 2;
   constexpr int IC = WC / 16, IK = WK / 16;
@@ -582,7 +577,6 @@ __global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(DevPlan p, 
   __shared__ __align__(16) u16 Xs[2][2][BC][KJ + BPAD];  // [plane][parity][col c][ring]
   __shared__ __align__(16) u16 Ts[2][2][BK][KJ + BPAD];  // [plane][parity][k][ring]
 
-  const WorkItem it = items[blockIdx.x];
   const MInfo mi = p.ms[it.m];
   const int m = mi.m;
   const int tid = threadIdx.x;
@@ -724,60 +718,134 @@ __global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(DevPlan p, 
 }
 
 // ---------------------------------------------------------------------------
-// Tile shapes and launchers
+// Kernels: work groups loop over the items (grid stride), each item with its
+// own plan and buffers.
 // ---------------------------------------------------------------------------
 
-constexpr int INV64_BM = 64, INV64_BN = 64, INV64_KI = 16, DIR64_BC = 64, DIR64_BK = 64, DIR64_KJ = 16;
-constexpr int INV32_BM = 128, INV32_BN = 128, INV32_KI = 16, DIR32_BC = 128, DIR32_BK = 64, DIR32_KJ = 16;
-constexpr int INVB_BM = 128, INVB_BN = 128, DIRB_BC = 128, DIRB_BK = 64;
-
-void legendre_tiles(int prec, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols) {
-  if (prec == SHT_FP64) {
-    *inv_rows = INV64_BM;
-    *inv_cols = INV64_BN;
-    *dir_rows = DIR64_BK;
-    *dir_cols = DIR64_BC;
-  } else if (prec == SHT_FP32) {
-    *inv_rows = INV32_BM;
-    *inv_cols = INV32_BN;
-    *dir_rows = DIR32_BK;
-    *dir_cols = DIR32_BC;
-  } else {
-    *inv_rows = INVB_BM;
-    *inv_cols = INVB_BN;
-    *dir_rows = DIRB_BK;
-    *dir_cols = DIRB_BC;
+template <typename T, int BM, int BN, int KI, int WCOL>
+__global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(const DevPlan* __restrict__ plans,
+                                                               const WorkItem* __restrict__ items, int nitems,
+                                                               const IoBind* __restrict__ io, IoBind io0) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const WorkItem it = items[w];
+    const DevPlan p = plans[it.plan];
+    const IoBind b = io ? io[it.plan] : io0;
+    inverse_tile<T, BM, BN, KI, WCOL>(p, it, (const T*)b.spec, (T*)b.ws);
   }
 }
 
-hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
-                                   const void* spec, void* four, hipStream_t s) {
-  if (nitems == 0) return hipSuccess;
-  if (prec == SHT_FP64)
-    hipLaunchKernelGGL((legendre_inverse_kernel<double, INV64_BM, INV64_BN, INV64_KI>), dim3(nitems), dim3(256), 0, s, p,
-                       items, (const double*)spec, (double*)four);
-  else if (prec == SHT_FP32)
-    hipLaunchKernelGGL((legendre_inverse_kernel<float, INV32_BM, INV32_BN, INV32_KI>), dim3(nitems), dim3(256), 0, s, p,
-                       items, (const float*)spec, (float*)four);
-  else
-    hipLaunchKernelGGL((legendre_inverse_bf16x3_kernel<INVB_BM, INVB_BN>), dim3(nitems), dim3(256), 0, s, p, items,
-                       plane, (const float*)spec, (float*)four);
-  return hipGetLastError();
+template <typename T, int BC, int BK, int KJ, int WKW>
+__global__ __launch_bounds__(256, 2) void legendre_direct_kernel(const DevPlan* __restrict__ plans,
+                                                              const WorkItem* __restrict__ items, int nitems,
+                                                              const IoBind* __restrict__ io, IoBind io0) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const WorkItem it = items[w];
+    const DevPlan p = plans[it.plan];
+    const IoBind b = io ? io[it.plan] : io0;
+    direct_tile<T, BC, BK, KJ, WKW>(p, it, (const T*)b.ws, (T*)b.spec);
+  }
 }
 
-hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
-                                  const void* four, void* spec, hipStream_t s) {
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(const DevPlan* __restrict__ plans,
+                                                                      const WorkItem* __restrict__ items, int nitems,
+                                                                      const IoBind* __restrict__ io, IoBind io0) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const WorkItem it = items[w];
+    const DevPlan p = plans[it.plan];
+    const IoBind b = io ? io[it.plan] : io0;
+    inverse_bf16x3_tile<BM, BN>(p, it, (const float*)b.spec, (float*)b.ws);
+  }
+}
+
+template <int BC, int BK>
+__global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(const DevPlan* __restrict__ plans,
+                                                                     const WorkItem* __restrict__ items, int nitems,
+                                                                     const IoBind* __restrict__ io, IoBind io0) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const WorkItem it = items[w];
+    const DevPlan p = plans[it.plan];
+    const IoBind b = io ? io[it.plan] : io0;
+    direct_bf16x3_tile<BC, BK>(p, it, (const float*)b.ws, (float*)b.spec);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Variants: (synthesis rows BM, columns BN, waves along columns) and
+// (analysis columns BC, k tile BK, waves along k).
+// ---------------------------------------------------------------------------
+
+#define INV_F64_C64 legendre_inverse_kernel<double, 64, 64, 16, 2>
+#define INV_F64_C32 legendre_inverse_kernel<double, 64, 32, 16, 1>
+#define INV_F32_C128 legendre_inverse_kernel<float, 128, 128, 16, 2>
+#define INV_F32_C64 legendre_inverse_kernel<float, 128, 64, 16, 2>
+#define INV_F32_C32 legendre_inverse_kernel<float, 128, 32, 16, 1>
+#define INV_BF16_C128 legendre_inverse_bf16x3_kernel<128, 128>
+#define DIR_F64_C64 legendre_direct_kernel<double, 64, 64, 16, 2>
+#define DIR_F64_C32 legendre_direct_kernel<double, 32, 64, 16, 4>
+#define DIR_F32_C128 legendre_direct_kernel<float, 128, 64, 16, 2>
+#define DIR_F32_C64 legendre_direct_kernel<float, 64, 64, 16, 2>
+#define DIR_F32_C32 legendre_direct_kernel<float, 32, 64, 16, 4>
+#define DIR_BF16_C128 legendre_direct_bf16x3_kernel<128, 64>
+
+bool legendre_variant_supported(int prec, int variant) {
+  if (prec == SHT_FP64) return variant == TILE_C64 || variant == TILE_C32;
+  if (prec == SHT_FP32) return variant >= 0 && variant < NUM_TILE_VARIANTS;
+  return variant == TILE_C128;
+}
+
+void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols) {
+  const int cols = variant == TILE_C128 ? 128 : variant == TILE_C64 ? 64 : 32;
+  *inv_rows = (prec == SHT_FP64) ? 64 : 128;
+  *inv_cols = cols;
+  *dir_rows = 64;
+  *dir_cols = cols;
+}
+
+template <typename K>
+static const void* fn(K k) {
+  return (const void*)k;
+}
+
+static const void* inverse_fn(int prec, int variant) {
+  if (prec == SHT_FP64) return variant == TILE_C32 ? fn(INV_F64_C32) : fn(INV_F64_C64);
+  if (prec == SHT_FP32)
+    return variant == TILE_C128 ? fn(INV_F32_C128) : variant == TILE_C64 ? fn(INV_F32_C64) : fn(INV_F32_C32);
+  return fn(INV_BF16_C128);
+}
+
+static const void* direct_fn(int prec, int variant) {
+  if (prec == SHT_FP64) return variant == TILE_C32 ? fn(DIR_F64_C32) : fn(DIR_F64_C64);
+  if (prec == SHT_FP32)
+    return variant == TILE_C128 ? fn(DIR_F32_C128) : variant == TILE_C64 ? fn(DIR_F32_C64) : fn(DIR_F32_C32);
+  return fn(DIR_BF16_C128);
+}
+
+int legendre_blocks_per_cu(int prec, int variant, bool inverse) {
+  int n = 0;
+  const void* f = inverse ? inverse_fn(prec, variant) : direct_fn(prec, variant);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess || n < 1) n = 1;
+  return n;
+}
+
+static hipError_t launch(const void* f, int grid_blocks, hipStream_t s, const DevPlan* plans, const WorkItem* items,
+                         int nitems, const IoBind* io, IoBind io0) {
+  void* args[] = {(void*)&plans, (void*)&items, (void*)&nitems, (void*)&io, (void*)&io0};
+  return hipLaunchKernel(f, dim3(grid_blocks), dim3(256), args, 0, s);
+}
+
+hipError_t launch_legendre_inverse(const DevPlan* plans, int prec, int variant, const WorkItem* items, int nitems,
+                                   const IoBind* io, IoBind io0, int grid_blocks, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  if (prec == SHT_FP64)
-    hipLaunchKernelGGL((legendre_direct_kernel<double, DIR64_BC, DIR64_BK, DIR64_KJ>), dim3(nitems), dim3(256), 0, s, p,
-                       items, (const double*)four, (double*)spec);
-  else if (prec == SHT_FP32)
-    hipLaunchKernelGGL((legendre_direct_kernel<float, DIR32_BC, DIR32_BK, DIR32_KJ>), dim3(nitems), dim3(256), 0, s, p,
-                       items, (const float*)four, (float*)spec);
-  else
-    hipLaunchKernelGGL((legendre_direct_bf16x3_kernel<DIRB_BC, DIRB_BK>), dim3(nitems), dim3(256), 0, s, p, items, plane,
-                       (const float*)four, (float*)spec);
-  return hipGetLastError();
+  if (!legendre_variant_supported(prec, variant)) return hipErrorInvalidValue;
+  return launch(inverse_fn(prec, variant), grid_blocks, s, plans, items, nitems, io, io0);
+}
+
+hipError_t launch_legendre_direct(const DevPlan* plans, int prec, int variant, const WorkItem* items, int nitems,
+                                  const IoBind* io, IoBind io0, int grid_blocks, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  if (!legendre_variant_supported(prec, variant)) return hipErrorInvalidValue;
+  return launch(direct_fn(prec, variant), grid_blocks, s, plans, items, nitems, io, io0);
 }
 
 }  // namespace shtmi

@@ -71,13 +71,36 @@ struct MInfo {
 };
 
 // A Legendre work item: wavenumber, tile along the table rows or columns,
-// tile along the field columns.
+// tile along the field columns, and the plan (index into the launch's plan
+// array) it belongs to.
 struct WorkItem {
   int32_t m;
   int32_t t0;  // first row (synthesis: ring row; analysis: k index)
   int32_t c0;  // first real column (2 f + re/im)
+  int32_t plan;
+};
+
+// An FFT work item: a ring (a north ring for analysis) and a chunk of fields.
+struct FftItem {
+  int32_t ring;
+  int32_t f0;
+  int32_t plan;
   int32_t pad;
 };
+
+// Device buffers of one transform: spectral [F][nspec] complex, grid
+// [F][npts] real, Fourier workspace.
+struct IoBind {
+  void* spec;
+  void* grid;
+  void* ws;
+  void* pad;
+};
+
+// Column-tile variants of the Legendre products (2F real columns per m):
+// 128, 64 or 32 columns per tile.  Narrow tiles keep small field counts
+// from wasting most of each MFMA.
+enum TileVariant { TILE_C128 = 0, TILE_C64 = 1, TILE_C32 = 2, NUM_TILE_VARIANTS = 3 };
 
 // Device-side view of a plan passed to kernels by value.
 struct DevPlan {
@@ -90,6 +113,7 @@ struct DevPlan {
   const double* w;
   const void* tab;      // Pbar tables (double, float, or bf16 hi/lo pairs)
   const void* fft;      // complex FFT tables in the data type
+  int64_t tab_plane;    // element offset of the lo plane of a BF16 split table
 };
 
 // ---------------------------------------------------------------------------
@@ -105,21 +129,28 @@ hipError_t launch_fft_tables(const DevPlan& p, int prec, const FftClass* d_cls, 
 hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& mi, int64_t plane,
                                       double* out, hipStream_t s);
 
-// legendre.hip
-// plane: element offset of the lo plane of a BF16 split table (unused otherwise)
-hipError_t launch_legendre_inverse(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
-                                   const void* spec, void* four, hipStream_t s);
-hipError_t launch_legendre_direct(const DevPlan& p, int prec, const WorkItem* items, int nitems, int64_t plane,
-                                  const void* four, void* spec, hipStream_t s);
-// tile shapes the work lists are built for
-void legendre_tiles(int prec, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols);
+// legendre.hip.  One launch covers `nitems` items of the plans in `plans`;
+// `grid_blocks` work groups loop over the items (grid stride).  Buffers come
+// from io[item.plan] when io is not null, else from io0.
+hipError_t launch_legendre_inverse(const DevPlan* plans, int prec, int variant, const WorkItem* items, int nitems,
+                                   const IoBind* io, IoBind io0, int grid_blocks, hipStream_t s);
+hipError_t launch_legendre_direct(const DevPlan* plans, int prec, int variant, const WorkItem* items, int nitems,
+                                  const IoBind* io, IoBind io0, int grid_blocks, hipStream_t s);
+// tile shape of a variant: rows (synthesis) / k (analysis) and columns
+void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols);
+bool legendre_variant_supported(int prec, int variant);
+// work groups per CU the kernel of a variant can keep resident
+int legendre_blocks_per_cu(int prec, int variant, bool inverse);
 
-// fft.hip
-hipError_t launch_fourier_synthesis(const DevPlan& p, int prec, const int2* items, int nitems, size_t lds,
-                                    const void* four, void* grid, hipStream_t s);
-hipError_t launch_fourier_analysis(const DevPlan& p, int prec, const int2* items, int nitems, size_t lds,
-                                   const void* grid, void* four, hipStream_t s);
+// fft.hip.  Same launch model; `nvirt` virtual work groups (fft_grid_blocks)
+// are spread over `grid_blocks` real ones.
+hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+                                    const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s);
+hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+                                   const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s);
 hipError_t fft_set_max_lds(size_t bytes);
 size_t fft_lds_bytes(int prec, int L, int mmax);
+size_t fft_grid_blocks(int nitems);
+int fft_blocks_per_cu(int prec, size_t lds);
 
 }  // namespace shtmi

@@ -11,11 +11,14 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "SHTError", "library", "LIB_PATH", "GRIDS", "PRECISIONS", "exported_symbols"]
+__all__ = ["Plan", "Batch", "SHTError", "library", "LIB_PATH", "GRIDS", "PRECISIONS", "TILES", "exported_symbols"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libshtmi.so")
 GRIDS = {"full": 0, "octahedral": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+TILES = {"c128": 0, "c64": 1, "c32": 2}
+BATCH_PERSISTENT = 1
+BATCH_GRAPH = 2
 
 _c_int_p = ctypes.POINTER(ctypes.c_int32)
 _c_i64_p = ctypes.POINTER(ctypes.c_int64)
@@ -37,7 +40,7 @@ class SHTInfo(ctypes.Structure):
         ("table_bytes", ctypes.c_int64),
         ("plan_bytes", ctypes.c_int64),
         ("elem_bytes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tile", ctypes.c_int32),
     ]
 
 
@@ -56,6 +59,17 @@ _SIGNATURES = {
     "sht_fourier_synthesis": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
     "sht_fourier_analysis": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
     "sht_legendre_direct": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 3),
+    "sht_plan_set_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "sht_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_void_p]),
+    "sht_batch_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "sht_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                      ctypes.c_void_p]),
+    "sht_batch_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sht_batch_direct": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sht_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "sht_batch_tiles": (ctypes.c_int, [ctypes.c_void_p, _c_int_p]),
+    "sht_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sht_last_hip_error": (ctypes.c_int, []),
 }
@@ -172,6 +186,15 @@ class Plan:
                "sht_plan_geometry")
         return {"mu": mu, "w": w, "nlon": nlon, "mmax": mmax, "ring_offset": off, "four_row": frow}
 
+    @property
+    def tile(self):
+        info = SHTInfo()
+        _check(self._lib.sht_plan_info(self._h, ctypes.byref(info)), "sht_plan_info")
+        return {v: k for k, v in TILES.items()}[info.tile]
+
+    def set_tile(self, tile, stream=None):
+        _check(self._lib.sht_plan_set_tile(self._h, TILES[tile], _stream_handle(stream)), "sht_plan_set_tile")
+
     def legendre_table(self, m):
         first = ctypes.c_int32()
         _check(self._lib.sht_plan_legendre_table(self._h, int(m), None, ctypes.byref(first)),
@@ -278,3 +301,71 @@ class Plan:
 
         t = workspace[: self.nfour * self.fpad * 2 * self.info.elem_bytes].view(self.dtype)
         return torch.view_as_complex(t.view(self.nfour // 2, 2, self.fpad, 2))
+
+
+class Batch:
+    """Several plans of one precision run in shared launches.  ``bind`` the
+    device buffers of every transform, then ``inverse`` / ``direct`` enqueue
+    all of them on the stream; ``tune`` picks each plan's tile variant by
+    timing."""
+
+    def __init__(self, plans, persistent=True, graph=False, stream=None):
+        lib = library()
+        self._lib = lib
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p._h.value for p in self.plans])
+        self._h = ctypes.c_void_p()
+        flags = (BATCH_PERSISTENT if persistent else 0) | (BATCH_GRAPH if graph else 0)
+        _check(lib.sht_batch_create(ctypes.byref(self._h), arr, len(self.plans), flags, _stream_handle(stream)),
+               "sht_batch_create")
+        self._bound = None
+
+    @property
+    def workspace_bytes(self):
+        return int(self._lib.sht_batch_workspace_size(self._h))
+
+    def bind(self, specs, grids, workspace=None):
+        import torch
+
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+        n = len(self.plans)
+        sp = (ctypes.c_void_p * n)(*[p._spec(s).value for p, s in zip(self.plans, specs)])
+        gp = (ctypes.c_void_p * n)(*[p._grid(g).value for p, g in zip(self.plans, grids)])
+        if workspace.numel() < self.workspace_bytes or workspace.dtype != torch.uint8:
+            raise ValueError("workspace too small")
+        _check(self._lib.sht_batch_bind(self._h, sp, gp, ctypes.c_void_p(workspace.data_ptr())), "sht_batch_bind")
+        self._bound = (list(specs), list(grids), workspace)
+        return workspace
+
+    def inverse(self, stream=None):
+        _check(self._lib.sht_batch_inverse(self._h, _stream_handle(stream)), "sht_batch_inverse")
+
+    def direct(self, stream=None):
+        _check(self._lib.sht_batch_direct(self._h, _stream_handle(stream)), "sht_batch_direct")
+
+    def tune(self, stream=None):
+        _check(self._lib.sht_batch_tune(self._h, _stream_handle(stream)), "sht_batch_tune")
+
+    def tiles(self):
+        out = (ctypes.c_int32 * len(self.plans))()
+        _check(self._lib.sht_batch_tiles(self._h, out), "sht_batch_tiles")
+        inv = {v: k for k, v in TILES.items()}
+        return [inv[x] for x in out]
+
+    def close(self):
+        if self._h:
+            _check(self._lib.sht_batch_destroy(self._h), "sht_batch_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
