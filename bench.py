@@ -219,6 +219,151 @@ def run_gpu(workload, precision, steps, warmup, seed=0):
     return out
 
 
+BATCH_TRUNCATIONS = (159, 255, 399, 639)
+
+
+def batch_shapes(n=64, seed=2024):
+    """The batched workload: n round trips, truncation uniform over
+    BATCH_TRUNCATIONS (octahedral grids), 1 to 137 fields each."""
+    rng = np.random.default_rng(seed)
+    Ns = rng.choice(BATCH_TRUNCATIONS, size=n)
+    Fs = rng.integers(1, 138, size=n)
+    return [(int(a), int(b)) for a, b in zip(Ns, Fs)]
+
+
+def run_batch(steps, warmup, precision="fp32"):
+    """Time the batched workload through sht_batch_* (persistent launches,
+    graph replay, tuned tiles) and the same transforms one call at a time.
+    Inputs: the seeded recipe with 4 distinct fields per transform, repeated
+    to its field count.  A step is a round trip in place: synthesis of the
+    spectral arrays, then analysis back into them."""
+    import torch
+
+    from paper_1908_06096_amd import sht
+    from paper_1908_06096_amd.inputs import spectral_coefficients
+
+    shapes = batch_shapes()
+    t0 = time.time()
+    plans = [sht.Plan(N, "octahedral", F, precision) for N, F in shapes]
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    specs = []
+    for i, (N, F) in enumerate(shapes):
+        d = min(F, 4)
+        a = spectral_coefficients(N, d, seed=1000 * i)[np.arange(F) % d]
+        specs.append(torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dt))
+    grids = [p.empty_grid() for p in plans]
+    fields = sum(F for _, F in shapes)
+    stream = torch.cuda.Stream()
+    out = {"transforms": len(shapes), "fields": fields, "precision": precision,
+           "truncations": {str(n): sum(1 for N, _ in shapes if N == n) for n in BATCH_TRUNCATIONS},
+           "plan_s": plan_s}
+    with torch.cuda.stream(stream):
+        b = sht.Batch(plans, persistent=True, graph=True)
+        ws = b.bind(specs, grids)
+        b.tune()
+        out["tiles"] = {t: b.tiles().count(t) for t in ("c128", "c64", "c32")}
+        for _ in range(warmup):
+            b.inverse()
+            b.direct()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        stream.synchronize()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            b.inverse()
+            ev[k][1].record(stream)
+            b.direct()
+            ev[k][2].record(stream)
+        stream.synchronize()
+        inv = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+        dirt = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+        out["ms_per_step"] = inv + dirt
+        out["inverse_ms"] = inv
+        out["direct_ms"] = dirt
+        out["value"] = 2.0 * fields / ((inv + dirt) * 1e-3)
+        # the same transforms, one plan call after another, on the same stream
+        wss = [p.empty_workspace() for p in plans]
+        for p, s_, g, w in zip(plans, specs, grids, wss):
+            p.inverse(s_, g, w)
+            p.direct(g, s_, w)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stream.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            for p, s_, g, w in zip(plans, specs, grids, wss):
+                p.inverse(s_, g, w)
+                p.direct(g, s_, w)
+        e1.record(stream)
+        stream.synchronize()
+        seq = e0.elapsed_time(e1) / steps
+        out["one_by_one_ms_per_step"] = seq
+        out["speedup_vs_one_by_one"] = seq / out["ms_per_step"]
+        b.close()
+        del ws, wss
+    for p in plans:
+        p.close()
+    log(f"[bench] batch: {out['ms_per_step']:.2f} ms per round trip of {len(shapes)} transforms "
+        f"({fields} fields), one by one {seq:.2f} ms")
+    return out
+
+
+def run_serving(n_requests=1000, slots=4, budget_gb=200.0, load=0.8):
+    """Serving stream: Poisson arrivals of round-trip requests, truncation
+    log-uniform over T79-T1279 snapped to a ladder of resident resolutions,
+    1-411 fields, FP32 or bf16x3 with probability 1/2 each.  The arrival rate
+    is `load` times the capacity measured on a burst of 100 requests that
+    all arrive at once; latency runs from arrival to completion."""
+    import torch
+
+    from paper_1908_06096_amd.serve import TRUNCATION_LADDER, GpuExecutor, Scheduler, draw_requests, percentile
+
+    ex = GpuExecutor(slots=slots)
+    t0 = time.time()
+    for N in TRUNCATION_LADDER:
+        for prec in ("fp32", "bf16x3"):
+            ex.warm(N, prec)
+    torch.cuda.synchronize()
+    warm_s = time.time() - t0
+    budget = int(budget_gb * 1e9)
+    sleep = lambda: time.sleep(2e-5)  # noqa: E731
+    burst = draw_requests(100, rate=0.0, seed=11)
+    t0 = time.perf_counter()
+    Scheduler(ex, slots, budget, idle=sleep).run(burst)
+    torch.cuda.synchronize()
+    cap = len(burst) / (time.perf_counter() - t0)
+    rate = load * cap
+    reqs = draw_requests(n_requests, rate=rate, seed=7)
+    sched = Scheduler(ex, slots, budget, idle=sleep)
+    t0 = time.perf_counter()
+    sched.run(reqs)
+    torch.cuda.synchronize()
+    span = time.perf_counter() - t0
+    lat = [r.latency for r in reqs]
+    fields = sum(r.fields for r in reqs)
+    ex.close()
+    out = {
+        "requests": len(reqs),
+        "slots": slots,
+        "arrival_rate_per_s": rate,
+        "capacity_per_s": cap,
+        "load": load,
+        "p50_latency_ms": percentile(lat, 50) * 1e3,
+        "p99_latency_ms": percentile(lat, 99) * 1e3,
+        "mean_latency_ms": float(np.mean(lat)) * 1e3,
+        "throughput_field_transforms_per_s": 2.0 * fields / span,
+        "makespan_s": span,
+        "peak_resident_gb": sched.peak / 1e9,
+        "budget_gb": budget_gb,
+        "warm_s": warm_s,
+        "resident_truncations": list(TRUNCATION_LADDER),
+    }
+    log(f"[bench] serving: {len(reqs)} requests at {rate:.1f}/s, p50 {out['p50_latency_ms']:.1f} ms, "
+        f"p99 {out['p99_latency_ms']:.1f} ms")
+    return out
+
+
 def oracle_sample_error(res, precision, seed=0, nrings=4):
     """Relative L2 of the GPU synthesis against the FP64 oracle on a few
     rings of field 0 (the oracle evaluates only those rings)."""
@@ -304,6 +449,8 @@ def main():
     ap.add_argument("--variants", default="bf16x3,fp64",
                     help="comma-separated other precisions to time on the same workload ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (reference for PMC byte counters)")
     ap.add_argument("--no-oracle-check", action="store_true")
@@ -377,6 +524,16 @@ def main():
         del r
     if variants:
         out["variants"] = variants
+    if not args.no_batch:
+        import torch
+
+        torch.cuda.empty_cache()
+        out["batch"] = run_batch(min(args.steps, 5), 1)
+    if not args.no_serving:
+        import torch
+
+        torch.cuda.empty_cache()
+        out["serving"] = run_serving()
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle sample")
         out["cpu_baseline"] = cpu_baseline(args.workload)

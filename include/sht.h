@@ -111,9 +111,10 @@ typedef struct sht_info {
   int64_t nfour;      /* sum over rings of (mmax_j + 1) */
   int64_t workspace_bytes;
   int64_t table_bytes;   /* resident Pbar tables */
-  int64_t plan_bytes;    /* every device byte the plan holds */
+  int64_t plan_bytes;    /* device bytes of the plan, shared tables included */
   int32_t elem_bytes;    /* 8 for SHT_FP64, 4 otherwise */
   int32_t tile;          /* Legendre column-tile variant in use (enum sht_tile) */
+  int64_t own_bytes;     /* device bytes of the plan without the shared tables */
 } sht_info;
 
 /* Column-tile variants of the Legendre products: the 2F real columns of a
@@ -138,6 +139,14 @@ enum sht_batch_flags {
  * for SHT_GRID_FULL), `nfields` >= 1.  On success *out receives the plan. */
 int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields,
                     int precision, void* hip_stream);
+
+/* A plan for `nfields` fields that shares every device table of `base`
+ * (same truncation, grid and precision): only its descriptor and work lists
+ * are new, so it is cheap to make and holds little memory.  The tables stay
+ * allocated until the last plan sharing them is destroyed; `base` may be
+ * destroyed first.  Synchronises `hip_stream`.  For callers that serve many
+ * field counts from resident tables. */
+int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hip_stream);
 
 /* Release a plan and its device memory (synchronises the device first). */
 int sht_plan_destroy(sht_plan_t plan);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -107,6 +108,20 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
+// Device tables of a (truncation, grid, precision): geometry metadata,
+// latitudes and weights, Pbar tables, FFT tables.  Shared by every plan made
+// from the same base plan; freed with the last of them.
+struct SharedTables {
+  void* arena = nullptr;
+  size_t bytes = 0;
+  ~SharedTables() {
+    if (arena) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(arena);
+    }
+  }
+};
+
 struct sht_plan_s {
   int N = 0, grid = 0, F = 0, prec = 0, nlat = 0, nh = 0, Fp = 0;
   int64_t npts = 0, nspec = 0, nfour = 0;
@@ -122,7 +137,8 @@ struct sht_plan_s {
   size_t tab_bytes = 0, fft_bytes = 0;
   size_t lds_syn = 0, lds_ana = 0;
   int max_Lp = 0;
-  // device
+  // device: shared tables, and this plan's own arena (descriptor, work lists)
+  std::shared_ptr<SharedTables> tables;
   void* arena = nullptr;
   size_t arena_bytes = 0;
   DevPlan dp{};
@@ -283,24 +299,62 @@ int build_host(sht_plan_s* p) {
   return SHT_OK;
 }
 
-int build_device(sht_plan_s* p, hipStream_t s) {
-  struct Part {
-    void** dst;
-    size_t bytes;
-  };
-  // the Legendre lists are sized for the largest list any variant needs, so
-  // that sht_plan_set_tile can switch variants in place
-  size_t inv_cap = p->inv_items.size(), dir_cap = p->dir_items.size();
+// Capacity of the Legendre work lists: the largest list any tile variant
+// needs, so that sht_plan_set_tile can switch variants in place.
+void list_capacity(const sht_plan_s* p, size_t* inv_cap, size_t* dir_cap) {
+  *inv_cap = p->inv_items.size();
+  *dir_cap = p->dir_items.size();
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
     if (!legendre_variant_supported(p->prec, v)) continue;
     std::vector<WorkItem> a, b;
     legendre_items(p, v, 0, &a, &b);
-    inv_cap = std::max(inv_cap, a.size());
-    dir_cap = std::max(dir_cap, b.size());
+    *inv_cap = std::max(*inv_cap, a.size());
+    *dir_cap = std::max(*dir_cap, b.size());
   }
-  void *v_self, *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft, *v_inv, *v_dir, *v_syn, *v_ana;
+}
+
+// The plan's own arena: its descriptor and work lists (tables already set).
+int build_own(sht_plan_s* p, hipStream_t s) {
+  size_t inv_cap, dir_cap;
+  list_capacity(p, &inv_cap, &dir_cap);
+  const size_t parts[5] = {sizeof(DevPlan), sizeof(WorkItem) * inv_cap, sizeof(WorkItem) * dir_cap,
+                           sizeof(FftItem) * p->syn_items.size(), sizeof(FftItem) * p->ana_items.size()};
+  size_t total = 0;
+  for (size_t q : parts) total += align256(q);
+  if (hipMalloc(&p->arena, total) != hipSuccess) {
+    (void)hipGetLastError();
+    p->arena = nullptr;
+    return SHT_ENOMEM;
+  }
+  p->arena_bytes = total;
+  char* o = (char*)p->arena;
+  void* ptr[5];
+  for (int i = 0; i < 5; ++i) {
+    ptr[i] = o;
+    o += align256(parts[i]);
+  }
+  p->d_self = (DevPlan*)ptr[0];
+  p->d_inv = (WorkItem*)ptr[1];
+  p->d_dir = (WorkItem*)ptr[2];
+  p->d_syn = (FftItem*)ptr[3];
+  p->d_ana = (FftItem*)ptr[4];
+  HIP_TRY(hipMemcpyAsync(p->d_self, &p->dp, sizeof(DevPlan), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->d_inv, p->inv_items.data(), sizeof(WorkItem) * p->inv_items.size(), hipMemcpyHostToDevice,
+                         s));
+  HIP_TRY(hipMemcpyAsync(p->d_dir, p->dir_items.data(), sizeof(WorkItem) * p->dir_items.size(), hipMemcpyHostToDevice,
+                         s));
+  HIP_TRY(hipMemcpyAsync(p->d_syn, p->syn_items.data(), parts[3], hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(p->d_ana, p->ana_items.data(), parts[4], hipMemcpyHostToDevice, s));
+  return SHT_OK;
+}
+
+int build_device(sht_plan_s* p, hipStream_t s) {
+  void *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft;
+  struct Part {
+    void** dst;
+    size_t bytes;
+  };
   const Part parts[] = {
-      {&v_self, sizeof(DevPlan)},
       {&v_rings, sizeof(RingInfo) * p->rings.size()},
       {&v_cls, sizeof(FftClass) * p->classes.size()},
       {&v_ms, sizeof(MInfo) * p->ms.size()},
@@ -308,22 +362,19 @@ int build_device(sht_plan_s* p, hipStream_t s) {
       {&v_w, sizeof(double) * p->nlat},
       {&v_tab, p->tab_bytes},
       {&v_fft, p->fft_bytes},
-      {&v_inv, sizeof(WorkItem) * inv_cap},
-      {&v_dir, sizeof(WorkItem) * dir_cap},
-      {&v_syn, sizeof(FftItem) * p->syn_items.size()},
-      {&v_ana, sizeof(FftItem) * p->ana_items.size()},
   };
   size_t total = 0;
   for (const Part& q : parts) total += align256(q.bytes);
-  if (hipMalloc(&p->arena, total) != hipSuccess) {
+  p->tables = std::make_shared<SharedTables>();
+  if (hipMalloc(&p->tables->arena, total) != hipSuccess) {
     (void)hipGetLastError();
-    p->arena = nullptr;
+    p->tables->arena = nullptr;
     return SHT_ENOMEM;
   }
-  p->arena_bytes = total;
+  p->tables->bytes = total;
   size_t o = 0;
   for (const Part& q : parts) {
-    *q.dst = (char*)p->arena + o;
+    *q.dst = (char*)p->tables->arena + o;
     o += align256(q.bytes);
   }
   DevPlan& d = p->dp;
@@ -342,24 +393,14 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   d.tab = v_tab;
   d.fft = v_fft;
   d.tab_plane = p->tab_plane;
-  p->d_self = (DevPlan*)v_self;
-  p->d_inv = (WorkItem*)v_inv;
-  p->d_dir = (WorkItem*)v_dir;
-  p->d_syn = (FftItem*)v_syn;
-  p->d_ana = (FftItem*)v_ana;
   p->d_ms = (MInfo*)v_ms;
   p->d_cls = (FftClass*)v_cls;
 
-  HIP_TRY(hipMemcpyAsync(v_self, &p->dp, sizeof(DevPlan), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_rings, p->rings.data(), parts[1].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), parts[2].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_ms, p->ms.data(), parts[3].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_inv, p->inv_items.data(), sizeof(WorkItem) * p->inv_items.size(), hipMemcpyHostToDevice,
-                         s));
-  HIP_TRY(hipMemcpyAsync(v_dir, p->dir_items.data(), sizeof(WorkItem) * p->dir_items.size(), hipMemcpyHostToDevice,
-                         s));
-  HIP_TRY(hipMemcpyAsync(v_syn, p->syn_items.data(), parts[10].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_ana, p->ana_items.data(), parts[11].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_rings, p->rings.data(), parts[0].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), parts[1].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_ms, p->ms.data(), parts[2].bytes, hipMemcpyHostToDevice, s));
+  int rc = build_own(p, s);
+  if (rc != SHT_OK) return rc;
 
   HIP_TRY(launch_gauss(p->nlat, (double*)v_mu, (double*)v_w, s));
   HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane, s));
@@ -588,6 +629,57 @@ int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int 
       (void)hipDeviceSynchronize();
       (void)hipFree(p->arena);
     }
+    delete p;  // releases the tables
+    return rc;
+  }
+  *out = p;
+  return SHT_OK;
+}
+
+int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hip_stream) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  if (!base || nfields < 1) return SHT_EINVAL;
+  sht_plan_s* p = new (std::nothrow) sht_plan_s();
+  if (!p) return SHT_ENOMEM;
+  p->N = base->N;
+  p->grid = base->grid;
+  p->prec = base->prec;
+  p->elem = base->elem;
+  p->nlat = base->nlat;
+  p->nh = base->nh;
+  p->npts = base->npts;
+  p->nspec = base->nspec;
+  p->nfour = base->nfour;
+  p->rings = base->rings;
+  p->classes = base->classes;
+  p->ms = base->ms;
+  p->ring_off = base->ring_off;
+  p->four_row = base->four_row;
+  p->tab_plane = base->tab_plane;
+  p->tab_bytes = base->tab_bytes;
+  p->fft_bytes = base->fft_bytes;
+  p->lds_syn = base->lds_syn;
+  p->lds_ana = base->lds_ana;
+  p->max_Lp = base->max_Lp;
+  p->tables = base->tables;
+  p->d_ms = base->d_ms;
+  p->d_cls = base->d_cls;
+  p->F = nfields;
+  p->Fp = (int)round_up(nfields, FPAD);
+  p->dp = base->dp;
+  p->dp.F = p->F;
+  p->dp.Fp = p->Fp;
+  p->variant = default_variant(p->prec, p->F);
+  legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
+  fft_items(p, 0, &p->syn_items, &p->ana_items);
+  int rc = build_own(p, (hipStream_t)hip_stream);
+  if (rc == SHT_OK) {
+    hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  if (rc != SHT_OK) {
+    if (p->arena) (void)hipFree(p->arena);
     delete p;
     return rc;
   }
@@ -603,7 +695,7 @@ int sht_plan_destroy(sht_plan_t p) {
     if (e == hipSuccess) e = hipFree(p->arena);
     if (e != hipSuccess) rc = hip_fail(e);
   }
-  delete p;
+  delete p;  // the tables go with the last plan that shares them
   return rc;
 }
 
@@ -621,7 +713,8 @@ int sht_plan_info(sht_plan_t p, sht_info* out) {
   out->nfour = p->nfour;
   out->workspace_bytes = (int64_t)sht_workspace_size(p);
   out->table_bytes = (int64_t)p->tab_bytes;
-  out->plan_bytes = (int64_t)p->arena_bytes;
+  out->plan_bytes = (int64_t)p->arena_bytes + (p->tables ? (int64_t)p->tables->bytes : 0);
+  out->own_bytes = (int64_t)p->arena_bytes;
   out->elem_bytes = p->elem;
   out->tile = p->variant;
   return SHT_OK;

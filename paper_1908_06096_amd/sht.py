@@ -41,12 +41,15 @@ class SHTInfo(ctypes.Structure):
         ("plan_bytes", ctypes.c_int64),
         ("elem_bytes", ctypes.c_int32),
         ("tile", ctypes.c_int32),
+        ("own_bytes", ctypes.c_int64),
     ]
 
 
 _SIGNATURES = {
     "sht_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_void_p]),
+    "sht_plan_create_like": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_void_p]),
     "sht_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sht_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SHTInfo)]),
     "sht_plan_geometry": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_int_p, _c_int_p, _c_i64_p,
@@ -124,12 +127,18 @@ class Plan:
     precision ('fp64' | 'fp32' | 'bf16x3').  Tables are computed on the GPU at
     creation and stay resident until ``close()``."""
 
-    def __init__(self, truncation, grid="full", nfields=1, precision="fp64", stream=None):
+    def __init__(self, truncation, grid="full", nfields=1, precision="fp64", stream=None, like=None):
         lib = library()
         self._lib = lib
         self._h = ctypes.c_void_p()
-        _check(lib.sht_plan_create(ctypes.byref(self._h), int(truncation), GRIDS[grid], int(nfields),
-                                   PRECISIONS[precision], _stream_handle(stream)), "sht_plan_create")
+        if like is not None:
+            # same tables as `like`, another field count
+            truncation, grid, precision = like.truncation, like.grid, like.precision
+            _check(lib.sht_plan_create_like(ctypes.byref(self._h), like._h, int(nfields), _stream_handle(stream)),
+                   "sht_plan_create_like")
+        else:
+            _check(lib.sht_plan_create(ctypes.byref(self._h), int(truncation), GRIDS[grid], int(nfields),
+                                       PRECISIONS[precision], _stream_handle(stream)), "sht_plan_create")
         info = SHTInfo()
         _check(lib.sht_plan_info(self._h, ctypes.byref(info)), "sht_plan_info")
         self.info = info
