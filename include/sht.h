@@ -126,8 +126,9 @@ typedef struct sht_batch_s* sht_batch_t;
 
 /* Batch flags. */
 enum sht_batch_flags {
-  SHT_BATCH_PERSISTENT = 1, /* each stage's launch uses only as many work groups as stay resident,
-                               each looping over the concatenated work list */
+  SHT_BATCH_PERSISTENT = 1, /* each Legendre launch uses only as many work groups as stay
+                               resident, each looping over the concatenated work list (FFT
+                               launches always give each (ring, field) its own work group) */
   SHT_BATCH_GRAPH = 2       /* capture the stage launches in a HIP graph on first use, replay after */
 };
 

@@ -544,16 +544,11 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
     if (persistent && ni) b->grid_inv[v] = std::min(ni, cus * legendre_blocks_per_cu(b->prec, v, true));
     if (persistent && nd) b->grid_dir[v] = std::min(nd, cus * legendre_blocks_per_cu(b->prec, v, false));
   }
-  const size_t vs = fft_grid_blocks((int)b->syn.size()), va = fft_grid_blocks((int)b->ana.size());
-  b->grid_syn = (int)vs;
-  b->grid_ana = (int)va;
-  if (persistent) {
-    // a multiple of 8 keeps each virtual block on the XCD its id selects
-    const int rs = std::max(8, cus * fft_blocks_per_cu(b->prec, b->lds_syn) / 8 * 8);
-    const int ra = std::max(8, cus * fft_blocks_per_cu(b->prec, b->lds_ana) / 8 * 8);
-    b->grid_syn = (int)std::min<size_t>(vs, rs);
-    b->grid_ana = (int)std::min<size_t>(va, ra);
-  }
+  // FFT launches keep one work group per (item, field): measured on uneven
+  // batches, letting the hardware hand out work groups balanced the rings'
+  // very different lengths better than a resident grid looping over them.
+  b->grid_syn = (int)fft_grid_blocks((int)b->syn.size());
+  b->grid_ana = (int)fft_grid_blocks((int)b->ana.size());
   return SHT_OK;
 }
 

@@ -49,10 +49,11 @@ __device__ inline C cscale(C a, T s) {
   return C{a.x * s, a.y * s};
 }
 
-// LDS index of FFT element i: one complex slot of padding after every 16
-// elements, so that the strided stores of a Stockham pass (stride R or Ns R
-// elements across lanes) spread over the banks instead of piling onto a few.
-__device__ inline int lds_ix(int i) { return i + (i >> 4); }
+// LDS index of FFT element i.  Kept unpadded: then the R reads and the R
+// writes of a butterfly sit at constant strides from one base address and
+// need no per-element address arithmetic (padding against bank conflicts
+// was measured and bought nothing, while costing that arithmetic).
+__device__ inline int lds_ix(int i) { return i; }
 
 // Forward DFT of R points in registers.  Radices 8, 9 and 16 are built from
 // smaller ones by one Cooley-Tukey step (even/odd halves for 8 and 16,
@@ -169,15 +170,21 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
   typedef typename V2T<T>::type C;
   constexpr int MAXB = FFT_REGS / R;
   const int nb = L / R;
+  // b mod Ns by multiply-high: for b < 2^14 and 1 < Ns <= 2^13,
+  // floor(b / Ns) = umulhi(b, ceil(2^32 / Ns)) exactly
+  const uint32_t magic = Ns > 1 ? 0xFFFFFFFFu / (uint32_t)Ns + 1u : 0u;
   C v[MAXB][R];
+  int kk[MAXB];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
     const int b = threadIdx.x + i * FFT_THREADS;
+    kk[i] = Ns > 1 ? b - (int)__umulhi((uint32_t)b, magic) * Ns : 0;
     if (b < nb) {
+      const C* src = buf + b;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_ix(b + r * nb)];
+      for (int r = 0; r < R; ++r) v[i][r] = src[r * nb];
       if (Ns > 1) {
-        const C* t = tw + (b % Ns) * (R - 1) - 1;
+        const C* t = tw + kk[i] * (R - 1) - 1;
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], t[r]);
       }
@@ -189,17 +196,17 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
     const int b = threadIdx.x + i * FFT_THREADS;
     if (b < nb) {
       butterfly<T, R>(v[i]);
-      const int k = b % Ns;
+      const int k = kk[i];
       const int d = (b - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int o = d + r * Ns;
         if constexpr (MODE == OUT_PLAIN) {
-          buf[lds_ix(o)] = v[i][r];
+          buf[o] = v[i][r];
         } else if constexpr (MODE == OUT_KHAT) {
-          buf[lds_ix(o)] = cconj(cmul(v[i][r], aux[o]));
+          buf[o] = cconj(cmul(v[i][r], aux[o]));
         } else {
-          if (o < h) buf[lds_ix(o)] = cmul(aux[o], cconj(v[i][r]));
+          if (o < h) buf[o] = cmul(aux[o], cconj(v[i][r]));
         }
       }
     }
@@ -389,7 +396,7 @@ __device__ __forceinline__ void analysis_field(const DevPlan& p, int ring, int f
 
 size_t fft_lds_bytes(int prec, int L, int mmax) {
   const size_t c = (prec == SHT_FP64) ? 16 : 8;
-  const size_t padded = (size_t)L + (size_t)L / 16 + 1;
+  const size_t padded = (size_t)L + 1;
   return c * (padded + (mmax >= 0 ? (size_t)mmax + 1 : 0));
 }
 

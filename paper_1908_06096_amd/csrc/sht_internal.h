@@ -25,8 +25,8 @@ constexpr int FPAD = 16;
 
 // FFT: threads per work group and complex values each thread may hold in
 // registers during one pass; together they bound the transform length.
-constexpr int FFT_THREADS = 256;
-constexpr int FFT_REGS = 32;
+constexpr int FFT_THREADS = 512;
+constexpr int FFT_REGS = 18;
 constexpr int FFT_MAX_RADICES = 20;
 
 // ---------------------------------------------------------------------------
