@@ -41,37 +41,64 @@ bool five_smooth(int64_t x) {
   return x == 1;
 }
 
-// Radix sequence for a 5-smooth length, fewest passes first: the power of
-// two as 16s plus one 2, 4 or 8; the power of three as 9s plus one 3; 5s.
-std::vector<int> radices(int L) {
+// Radices the passes can use (each has a register butterfly).
+constexpr int kRadices[] = {20, 18, 16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+
+// A pass of radix R over L points fits `threads` threads when its L / R
+// butterflies fit the FFT_REGS / R butterflies each thread holds.
+bool radix_fits(int L, int R, int threads) {
+  return (int64_t)(L / R) <= (int64_t)(FFT_REGS / R) * threads;
+}
+
+// Fewest passes for the cofactor x of L (memoised), and the first radix.
+int fewest_passes(int L, int x, int threads, std::map<int, std::pair<int, int>>* memo) {
+  if (x == 1) return 0;
+  auto it = memo->find(x);
+  if (it != memo->end()) return it->second.first;
+  int bp = 1 << 20, br = 0;
+  for (int R : kRadices)
+    if (x % R == 0 && radix_fits(L, R, threads)) {
+      const int c = 1 + fewest_passes(L, x / R, threads, memo);
+      if (c < bp) {
+        bp = c;
+        br = R;
+      }
+    }
+  (*memo)[x] = {bp, br};
+  return bp;
+}
+
+// Radix sequence for a 5-smooth length: the fewest passes that all fit
+// `threads` threads, the larger radix first among equally short sequences.
+// Each pass is one LDS round trip and two barriers, which is what the
+// transforms' time goes to.  Empty when no sequence fits.
+std::vector<int> radices(int L, int threads = FFT_THREADS) {
+  std::map<int, std::pair<int, int>> memo;
   std::vector<int> r;
-  int x = L, e2 = 0;
-  while (x % 2 == 0) {
-    x /= 2;
-    ++e2;
-  }
-  for (; e2 >= 4; e2 -= 4) r.push_back(16);
-  if (e2 > 0) r.push_back(1 << e2);
-  while (x % 9 == 0) {
-    r.push_back(9);
-    x /= 9;
-  }
-  if (x % 3 == 0) {
-    r.push_back(3);
-    x /= 3;
-  }
-  while (x % 5 == 0) {
-    r.push_back(5);
-    x /= 5;
-  }
+  if (fewest_passes(L, L, threads, &memo) >= (1 << 20)) return r;
+  for (int x = L; x > 1; x /= memo[x].second) r.push_back(memo[x].second);
   return r;
 }
 
-// Every Stockham pass must fit FFT_REGS complex values per thread.
-bool fits_registers(int L, const std::vector<int>& rad) {
-  for (int R : rad)
-    if ((int64_t)(L / R) > (int64_t)(FFT_REGS / R) * FFT_THREADS) return false;
-  return true;
+// Chirp-z length for half length h: among the 5-smooth L >= 2h - 1 (up to a
+// quarter above), the one with the least L (passes + 1), the LDS traffic of
+// the two transforms and their element-wise steps.  0 when none fits.
+int bluestein_length(int h) {
+  const int64_t lo = 2 * (int64_t)h - 1;
+  const int64_t hi = lo + std::max<int64_t>(64, lo / 4);
+  int best = 0;
+  double best_cost = 0;
+  for (int64_t L = lo; L <= hi && L < (1 << 14); ++L) {
+    if (!five_smooth(L)) continue;
+    const std::vector<int> r = radices((int)L);
+    if (r.empty()) continue;
+    const double cost = (double)L * (double)(r.size() + 1);
+    if (best == 0 || cost < best_cost) {
+      best = (int)L;
+      best_cost = cost;
+    }
+  }
+  return best;
 }
 
 // The dynamic-LDS limit is a property of the kernel functions: raise it to
@@ -176,12 +203,48 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
     return p->classes[p->rings[a].cls].L > p->classes[p->rings[b].cls].L;
   });
-  const int fchunk = 16;
   for (int j : order)
-    for (int f0 = 0; f0 < p->F; f0 += fchunk) {
-      syn->push_back(FftItem{j, f0, plan, 0});
-      if (j < p->nh) ana->push_back(FftItem{j, f0, plan, 0});
+    for (int f0 = 0; f0 < p->F; f0 += FFT_FCHUNK) {
+      const int fend = std::min(f0 + FFT_FCHUNK, p->F);
+      syn->push_back(FftItem{j, f0, plan, fend});
+      if (j < p->nh) ana->push_back(FftItem{j, f0, plan, fend});
     }
+}
+
+// Work-group list from a list of chunks (items of up to FFT_FCHUNK fields,
+// in launch order): a chunk of a class with G fields per work group becomes
+// ceil(n / G) work groups.  Work groups go to the XCDs round-robin by id, so
+// the groups of one chunk are given ids congruent modulo NUM_XCD, 8 chunks
+// side by side (empty slots where a chunk has fewer groups than the others
+// of its eight): they run on one XCD at the same time, and their strided
+// reads and writes of the chunk's Fourier rows (fields are the innermost
+// index) meet in that XCD's L2.
+constexpr int NUM_XCD = 8;
+
+void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
+  std::vector<FftItem> chunks;
+  chunks.swap(*items);
+  for (size_t c0 = 0; c0 < chunks.size(); c0 += NUM_XCD) {
+    const int nc = (int)std::min<size_t>(NUM_XCD, chunks.size() - c0);
+    int G[NUM_XCD], ng[NUM_XCD], most = 0;
+    for (int k = 0; k < nc; ++k) {
+      const FftItem& c = chunks[c0 + k];
+      const sht_plan_s* p = plans[c.plan];
+      G[k] = p->classes[p->rings[c.ring].cls].G;
+      ng[k] = (c.fend - c.f0 + G[k] - 1) / G[k];
+      most = std::max(most, ng[k]);
+    }
+    for (int j = 0; j < most; ++j)
+      for (int k = 0; k < NUM_XCD; ++k) {
+        if (k < nc && j < ng[k]) {
+          const FftItem& c = chunks[c0 + k];
+          const int f0 = c.f0 + j * G[k];
+          items->push_back(FftItem{c.ring, f0, c.plan, std::min(f0 + G[k], c.fend)});
+        } else {
+          items->push_back(FftItem{-1, 0, 0, 0});
+        }
+      }
+  }
 }
 
 int build_host(sht_plan_s* p) {
@@ -230,13 +293,11 @@ int build_host(sht_plan_s* p) {
       c.L = h;
       c.bluestein = 0;
     } else {
-      int64_t L = 2 * (int64_t)h - 1;
-      while (!five_smooth(L)) ++L;
-      c.L = (int)L;
+      c.L = bluestein_length(h);
       c.bluestein = 1;
     }
-    std::vector<int> rad = radices(c.L);
-    if ((int)rad.size() > FFT_MAX_RADICES || !fits_registers(c.L, rad)) return SHT_EUNSUPPORTED;
+    std::vector<int> rad = c.L > 0 ? radices(c.L) : std::vector<int>();
+    if (rad.empty() || (int)rad.size() > FFT_MAX_RADICES) return SHT_EUNSUPPORTED;
     c.nrad = (int)rad.size();
     for (size_t q = 0; q < rad.size(); ++q) c.rad[q] = rad[q];
     c.root_off = off;
@@ -252,12 +313,43 @@ int build_host(sht_plan_s* p) {
     p->classes.push_back(c);
   }
   p->fft_bytes = (size_t)off * csize;
+  // Fields per work group: the most (up to FFT_MAX_G) whose FFT_THREADS / G
+  // threads still hold every pass and whose LDS fits the budget: the most
+  // LDS that keeps the occupancy the longest class has with G = 1.
+  // A ring of class h carries mmax = min(N, h - 1).
+  size_t need1 = 0;
+  for (const FftClass& c : p->classes)
+    need1 = std::max(need1, fft_lds_bytes(p->prec, c.L, std::min(N, c.h - 1), 1));
+  size_t budget = need1;
+  {
+    const int occ = fft_blocks_per_cu(p->prec, need1);
+    for (size_t b = need1 + 1024; b <= 160 * 1024; b += 1024) {
+      if (fft_blocks_per_cu(p->prec, b) < occ) break;
+      budget = b;
+    }
+  }
+  // A G > 1 must keep the pass count of G = 1 (its radices may differ).
+  for (FftClass& c : p->classes) {
+    int gs = 0;
+    std::vector<int> best(c.rad, c.rad + c.nrad);
+    for (int s = 0; (2 << s) <= FFT_MAX_G; ++s) {
+      const int G = 2 << s;
+      const std::vector<int> rad = radices(c.L, FFT_THREADS / G);
+      if (rad.empty() || rad.size() > (size_t)c.nrad) break;
+      if (fft_lds_bytes(p->prec, c.L, std::min(N, c.h - 1), G) > budget) break;
+      gs = s + 1;
+      best = rad;
+    }
+    c.G = 1 << gs;
+    c.gshift = gs;
+    for (size_t q = 0; q < best.size(); ++q) c.rad[q] = best[q];
+  }
   for (auto& r : p->rings) {
     const int h = r.nlon / 2;
     r.cls = (int)(std::lower_bound(hs.begin(), hs.end(), h) - hs.begin());
     const FftClass& c = p->classes[r.cls];
-    p->lds_syn = std::max(p->lds_syn, fft_lds_bytes(p->prec, c.L, -1));
-    p->lds_ana = std::max(p->lds_ana, fft_lds_bytes(p->prec, c.L, r.mmax));
+    p->lds_syn = std::max(p->lds_syn, fft_lds_bytes(p->prec, c.L, -1, c.G));
+    p->lds_ana = std::max(p->lds_ana, fft_lds_bytes(p->prec, c.L, r.mmax, c.G));
   }
   if (p->lds_ana > 160 * 1024) return SHT_EUNSUPPORTED;
 
@@ -296,6 +388,8 @@ int build_host(sht_plan_s* p) {
   p->variant = default_variant(p->prec, p->F);
   legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
   fft_items(p, 0, &p->syn_items, &p->ana_items);
+  fft_arrange(&p, &p->syn_items);
+  fft_arrange(&p, &p->ana_items);
   return SHT_OK;
 }
 
@@ -490,6 +584,8 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
                    [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
   std::stable_sort(b->ana.begin(), b->ana.end(),
                    [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
+  fft_arrange(b->plans.data(), &b->syn);
+  fft_arrange(b->plans.data(), &b->ana);
 
   destroy_graphs(b);
   if (b->arena) {
@@ -544,9 +640,9 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
     if (persistent && ni) b->grid_inv[v] = std::min(ni, cus * legendre_blocks_per_cu(b->prec, v, true));
     if (persistent && nd) b->grid_dir[v] = std::min(nd, cus * legendre_blocks_per_cu(b->prec, v, false));
   }
-  // FFT launches keep one work group per (item, field): measured on uneven
-  // batches, letting the hardware hand out work groups balanced the rings'
-  // very different lengths better than a resident grid looping over them.
+  // FFT launches keep one work group per item: measured on uneven batches,
+  // letting the hardware hand out work groups balanced the rings' very
+  // different lengths better than a resident grid looping over them.
   b->grid_syn = (int)fft_grid_blocks((int)b->syn.size());
   b->grid_ana = (int)fft_grid_blocks((int)b->ana.size());
   return SHT_OK;
@@ -668,6 +764,8 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->variant = default_variant(p->prec, p->F);
   legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
   fft_items(p, 0, &p->syn_items, &p->ana_items);
+  fft_arrange(&p, &p->syn_items);
+  fft_arrange(&p, &p->ana_items);
   int rc = build_own(p, (hipStream_t)hip_stream);
   if (rc == SHT_OK) {
     hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);

@@ -49,15 +49,91 @@ __device__ inline C cscale(C a, T s) {
   return C{a.x * s, a.y * s};
 }
 
-// LDS index of FFT element i.  Kept unpadded: then the R reads and the R
-// writes of a butterfly sit at constant strides from one base address and
-// need no per-element address arithmetic (padding against bank conflicts
-// was measured and bought nothing, while costing that arithmetic).
-__device__ inline int lds_ix(int i) { return i; }
+// LDS slot of FFT element i: one spare slot after every 2^FFT_PAD_SHIFT
+// elements.  The early Stockham passes write with a lane stride of R
+// elements (R Ns with Ns < 64), which unpadded would put most lanes of a
+// wave on the same banks; the spare slots spread them.  A transform of L
+// elements spans lds_span(L) slots.
+constexpr int FFT_PAD_SHIFT = 4;
+__host__ __device__ constexpr int lds_ix(int i) { return i + (i >> FFT_PAD_SHIFT); }
+__host__ __device__ constexpr int lds_span(int L) { return lds_ix(L - 1) + 1; }
 
-// Forward DFT of R points in registers.  Radices 8, 9 and 16 are built from
-// smaller ones by one Cooley-Tukey step (even/odd halves for 8 and 16,
-// 3 x 3 for 9).
+// exp(-2 pi i j / R) at compile time: the angle is reduced exactly to
+// |r| <= pi/4 from the nearest quarter turn (4j - qR is an integer), then
+// sine and cosine of r are summed as Taylor series to double precision.
+struct UnitRoot {
+  double c, s;  // cos and sin of 2 pi j / R; the root is c - i s
+};
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double taylor_sin(double x) {
+  double term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double taylor_cos(double x) {
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+constexpr UnitRoot unit_root(int j, int R) {
+  j = ((j % R) + R) % R;
+  const int q = (8 * j + R) / (2 * R);  // nearest integer to 4 j / R
+  const double r = (kPi / 2) * (double)(4 * j - q * R) / (double)R;
+  const double c = taylor_cos(r), sn = taylor_sin(r);
+  switch (q & 3) {
+    case 0: return UnitRoot{c, sn};
+    case 1: return UnitRoot{-sn, c};
+    case 2: return UnitRoot{-c, -sn};
+    default: return UnitRoot{sn, -c};
+  }
+}
+
+template <typename T, int R>
+__device__ inline void butterfly(typename V2T<T>::type* v);
+
+// One Cooley-Tukey step for R = R1 R2 in registers: with n = R2 n1 + n2 and
+// k = k1 + R1 k2,
+//   X[k] = sum_n2 W_R2^(n2 k2) W_R^(n2 k1) sum_n1 x[n] W_R1^(n1 k1),
+// i.e. R2 DFTs of length R1, twiddles W_R^(n2 k1), R1 DFTs of length R2.
+template <typename T, int R1, int R2>
+__device__ inline void butterfly_ct(typename V2T<T>::type* v) {
+  typedef typename V2T<T>::type C;
+  constexpr int R = R1 * R2;
+  C y[R2][R1];
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) y[n2][n1] = v[R2 * n1 + n2];
+    butterfly<T, R1>(y[n2]);
+  }
+#pragma unroll
+  for (int n2 = 1; n2 < R2; ++n2) {
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) {
+      const UnitRoot w = unit_root(n2 * k1, R);
+      y[n2][k1] = cmul(y[n2][k1], C{(T)w.c, (T)-w.s});
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    C t[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) t[n2] = y[n2][k1];
+    butterfly<T, R2>(t);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = t[k2];
+  }
+}
+
+// Forward DFT of R points in registers.  Radices 2, 3, 4 and 5 are written
+// out; 8 and 16 take one even/odd step, 9 a 3 x 3 step, and the composite
+// radices 6, 10, 12, 15, 18 and 20 the generic step above.
 template <typename T, int R>
 __device__ inline void butterfly(typename V2T<T>::type* v) {
   typedef typename V2T<T>::type C;
@@ -148,6 +224,20 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
       v[k1 + 3] = t[1];
       v[k1 + 6] = t[2];
     }
+  } else if constexpr (R == 6) {
+    butterfly_ct<T, 3, 2>(v);
+  } else if constexpr (R == 10) {
+    butterfly_ct<T, 5, 2>(v);
+  } else if constexpr (R == 12) {
+    butterfly_ct<T, 4, 3>(v);
+  } else if constexpr (R == 15) {
+    butterfly_ct<T, 5, 3>(v);
+  } else if constexpr (R == 18) {
+    butterfly_ct<T, 9, 2>(v);
+  } else if constexpr (R == 20) {
+    butterfly_ct<T, 5, 4>(v);
+  } else {
+    static_assert(R == 0, "unsupported radix");
   }
 }
 
@@ -155,18 +245,20 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
 enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2 };
 
 // One Stockham pass of radix R over L points in LDS, after Ns points have
-// been combined: butterfly b reads x[b + r L/R], twiddles input r by
+// been combined, carried out by the nt threads (thread lt) that own this
+// transform: butterfly b reads x[b + r L/R], twiddles input r by
 // exp(-2 pi i r (b mod Ns) / (Ns R)) (the pass's table holds these at
 // (b mod Ns)(R - 1) + r - 1, so lanes with consecutive b read consecutive
-// entries) and writes y[(b / Ns) Ns R + b mod Ns + r Ns].  All reads of the pass land in registers before the barrier, so
-// one LDS buffer suffices.  OUT_KHAT stores conj(y khat) and OUT_CHIRP
-// stores c_q conj(y_q) for q < h (the element-wise steps of the chirp-z
-// convolution).  Each instantiation is its own non-inlined function so that
-// its registers are allocated for it alone.
+// entries) and writes y[(b / Ns) Ns R + b mod Ns + r Ns].  All reads of the
+// pass land in registers before the barrier, so one LDS buffer suffices.
+// OUT_KHAT stores conj(y khat) and OUT_CHIRP stores c_q conj(y_q) for q < h
+// (the element-wise steps of the chirp-z convolution).  Each instantiation
+// is its own non-inlined function so that its registers are allocated for
+// it alone.  Every thread of the work group calls it (the barriers).
 template <typename T, int R, int MODE>
 __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
-                                           int h) {
+                                           int h, int lt, int nt) {
   typedef typename V2T<T>::type C;
   constexpr int MAXB = FFT_REGS / R;
   const int nb = L / R;
@@ -177,23 +269,22 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
   int kk[MAXB];
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int b = threadIdx.x + i * FFT_THREADS;
+    const int b = lt + i * nt;
     kk[i] = Ns > 1 ? b - (int)__umulhi((uint32_t)b, magic) * Ns : 0;
     if (b < nb) {
-      const C* src = buf + b;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src[r * nb];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_ix(b + r * nb)];
       if (Ns > 1) {
         const C* t = tw + kk[i] * (R - 1) - 1;
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], t[r]);
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], gload(t + r));
       }
     }
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < MAXB; ++i) {
-    const int b = threadIdx.x + i * FFT_THREADS;
+    const int b = lt + i * nt;
     if (b < nb) {
       butterfly<T, R>(v[i]);
       const int k = kk[i];
@@ -202,11 +293,11 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
       for (int r = 0; r < R; ++r) {
         const int o = d + r * Ns;
         if constexpr (MODE == OUT_PLAIN) {
-          buf[o] = v[i][r];
+          buf[lds_ix(o)] = v[i][r];
         } else if constexpr (MODE == OUT_KHAT) {
-          buf[o] = cconj(cmul(v[i][r], aux[o]));
+          buf[lds_ix(o)] = cconj(cmul(v[i][r], gload(aux + o)));
         } else {
-          if (o < h) buf[o] = cmul(aux[o], cconj(v[i][r]));
+          if (o < h) buf[lds_ix(o)] = cmul(gload(aux + o), cconj(v[i][r]));
         }
       }
     }
@@ -216,15 +307,22 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
 
 template <typename T, int MODE>
 __device__ inline void pass_dispatch(int R, typename V2T<T>::type* buf, int L, int Ns,
-                                     const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h) {
+                                     const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h,
+                                     int lt, int nt) {
   switch (R) {
-    case 16: stockham_pass<T, 16, MODE>(buf, L, Ns, tw, aux, h); break;
-    case 9: stockham_pass<T, 9, MODE>(buf, L, Ns, tw, aux, h); break;
-    case 8: stockham_pass<T, 8, MODE>(buf, L, Ns, tw, aux, h); break;
-    case 5: stockham_pass<T, 5, MODE>(buf, L, Ns, tw, aux, h); break;
-    case 4: stockham_pass<T, 4, MODE>(buf, L, Ns, tw, aux, h); break;
-    case 3: stockham_pass<T, 3, MODE>(buf, L, Ns, tw, aux, h); break;
-    default: stockham_pass<T, 2, MODE>(buf, L, Ns, tw, aux, h); break;
+    case 20: stockham_pass<T, 20, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 18: stockham_pass<T, 18, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 16: stockham_pass<T, 16, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 15: stockham_pass<T, 15, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 12: stockham_pass<T, 12, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 10: stockham_pass<T, 10, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 6: stockham_pass<T, 6, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 9: stockham_pass<T, 9, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 8: stockham_pass<T, 8, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 5: stockham_pass<T, 5, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 4: stockham_pass<T, 4, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 3: stockham_pass<T, 3, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    default: stockham_pass<T, 2, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
   }
 }
 
@@ -232,70 +330,59 @@ __device__ inline void pass_dispatch(int R, typename V2T<T>::type* buf, int L, i
 // pass applies MODE.
 template <typename T, int MODE>
 __device__ void fft_lds(typename V2T<T>::type* buf, int L, int nrad, const int32_t* rad,
-                        const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h) {
+                        const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h, int lt, int nt) {
   int Ns = 1;
   for (int q = 0; q < nrad; ++q) {
-    const int R = rad[q];
-    if (q == nrad - 1) pass_dispatch<T, MODE>(R, buf, L, Ns, tw, aux, h);
-    else pass_dispatch<T, OUT_PLAIN>(R, buf, L, Ns, tw, aux, h);
+    const int R = gload(rad + q);
+    if (q == nrad - 1) pass_dispatch<T, MODE>(R, buf, L, Ns, tw, aux, h, lt, nt);
+    else pass_dispatch<T, OUT_PLAIN>(R, buf, L, Ns, tw, aux, h, lt, nt);
     tw += Ns * (R - 1);
     Ns *= R;
   }
 }
 
-// Forward complex DFT of length h.  On entry buf[t] holds z_t, t < h,
-// already multiplied by the chirp c_t for chirp-z classes, whose entries
-// h <= t < L must be zero.  On exit buf[q], q < h, holds Z_q.  Chirp-z:
+// Forward complex DFT of length h.  On entry buf[lds_ix(t)] holds z_t,
+// t < h, already multiplied by the chirp c_t for chirp-z classes, whose
+// entries h <= t < L must be zero.  On exit buf[lds_ix(q)], q < h, holds
+// Z_q.  Chirp-z:
 // A = DFT_L(a), B = conj(A khat), Z_q = c_q conj(DFT_L(B))_q.
 template <typename T>
 __device__ void dft_h(typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
-                      const typename V2T<T>::type* tabs) {
+                      const typename V2T<T>::type* tabs, int lt, int nt) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
   if (!c.bluestein) {
-    fft_lds<T, OUT_PLAIN>(buf, c.L, c.nrad, rad, tw, nullptr, c.h);
+    fft_lds<T, OUT_PLAIN>(buf, c.L, c.nrad, rad, tw, nullptr, c.h, lt, nt);
     return;
   }
-  fft_lds<T, OUT_KHAT>(buf, c.L, c.nrad, rad, tw, tabs + c.khat_off, c.h);
-  fft_lds<T, OUT_CHIRP>(buf, c.L, c.nrad, rad, tw, tabs + c.chirp_off, c.h);
+  fft_lds<T, OUT_KHAT>(buf, c.L, c.nrad, rad, tw, tabs + c.khat_off, c.h, lt, nt);
+  fft_lds<T, OUT_CHIRP>(buf, c.L, c.nrad, rad, tw, tabs + c.chirp_off, c.h, lt, nt);
 }
 
-constexpr int FFT_FCHUNK = 16;
-constexpr int NUM_XCD = 8;
+// Sweeps over a ring (gathers, scatters) issue the global loads of
+// FFT_SWEEP iterations before using any of them.
+constexpr int FFT_SWEEP = 4;
 
-// Work-group -> (work item, field).  One work item is a ring (pair) and a
-// chunk of FFT_FCHUNK fields that share cache lines of the Fourier buffer
-// (fields are its innermost index).  Work groups are handed to the XCDs
-// round-robin by id, so the FFT_FCHUNK fields of an item get ids that are
-// congruent modulo NUM_XCD and adjacent in dispatch order: they run on one
-// XCD at the same time and their strided accesses meet in that XCD's L2.
-__device__ inline bool decode_block(int bid, int nitems, int* item, int* slot) {
-  const int grp = bid / (NUM_XCD * FFT_FCHUNK);
-  const int r = bid - grp * (NUM_XCD * FFT_FCHUNK);
-  *item = grp * NUM_XCD + r % NUM_XCD;
-  *slot = r / NUM_XCD;
-  return *item < nitems;
-}
-
-__host__ __device__ inline size_t fft_grid_blocks_dev(int nitems) {
-  return (size_t)((nitems + NUM_XCD - 1) / NUM_XCD) * NUM_XCD * FFT_FCHUNK;
-}
-
-size_t fft_grid_blocks(int nitems) { return fft_grid_blocks_dev(nitems); }
+// Launch size: one work group per item.
+size_t fft_grid_blocks(int nitems) { return (size_t)nitems; }
 
 // ---------------------------------------------------------------------------
-// Synthesis: ring j, one field of the chunk [f0, f0 + FFT_FCHUNK).
+// Synthesis: ring j, the fields [f0, fend) side by side (fend - f0 <= G).
 //   X_m = c_m for m <= mmax_j (Im c_0 dropped), 0 above, Nyquist 0;
 //   Z_q = (X_q + conj X_{h-q}) + i w^q (X_q - conj X_{h-q}),  w = exp(2 pi i / n);
 //   z = inverse DFT_h(Z) = conj(DFT_h(conj Z));  g_{2t} = Re z_t,  g_{2t+1} = Im z_t.
+// Field f0 + s owns LDS slots [s S, (s + 1) S), S = lds_span(L), and threads
+// [s nt, (s + 1) nt).
+// The gather of X reads element e as (q = e / G, s = e mod G), so that
+// neighbouring lanes read neighbouring fields of one Fourier row.
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ __forceinline__ void synthesis_field(const DevPlan& p, int ring, int f, const T* __restrict__ four,
-                                                T* __restrict__ grid) {
+__device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int fb, int fend,
+                                                const T* __restrict__ four, T* __restrict__ grid) {
   typedef typename V2T<T>::type C;
   extern __shared__ __align__(16) unsigned char smem[];
-  const RingInfo ri = p.rings[ring];
-  const FftClass cl = p.classes[ri.cls];
+  const RingInfo ri = gload(p.rings + ring);
+  const FftClass cl = gload(p.classes + ri.cls);
   const int32_t* rad = p.classes[ri.cls].rad;
   const C* tabs = (const C*)p.fft;
   C* buf = (C*)smem;
@@ -305,88 +392,145 @@ __device__ __forceinline__ void synthesis_field(const DevPlan& p, int ring, int 
   const int h = cl.h, mmax = ri.mmax, L = cl.L;
   const bool blue = cl.bluestein;
   const int64_t Fp = p.Fp;
+  const int gs = cl.gshift, G = 1 << gs;
+  const int nt = FFT_THREADS >> gs;
+  const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
+  const int Q = blue ? L : h;
+  const int S = lds_span(L);
   {
-    const C* cf = fc + ri.frow * Fp + f;
-    for (int q = threadIdx.x; q < (blue ? L : h); q += FFT_THREADS) {
-      C y = C{0, 0};
-      if (q < h) {
-        C xq = (q <= mmax) ? cf[q * Fp] : C{0, 0};
-        if (q == 0) xq.y = 0;
-        const int q2 = h - q;
-        const C xr = (q >= 1 && q2 <= mmax) ? cconj(cf[q2 * Fp]) : C{0, 0};
-        const C s = cadd(xq, xr);
-        const C t = cmul(cconj(post[q]), csub(xq, xr));
-        y = C{s.x - t.y, -(s.y + t.x)};  // conj(s + i t)
-        if (blue) y = cmul(y, chirp[q]);
+    const int n = Q << gs;
+    for (int e0 = threadIdx.x; e0 < n; e0 += FFT_SWEEP * FFT_THREADS) {
+      C xq[FFT_SWEEP], xr[FFT_SWEEP], pq[FFT_SWEEP], cq[FFT_SWEEP];
+#pragma unroll
+      for (int u = 0; u < FFT_SWEEP; ++u) {
+        const int e = e0 + u * FFT_THREADS;
+        const int s = e & (G - 1), q = e >> gs, q2 = h - q;
+        const bool ok = e < n && q < h && fb + s < fend;
+        const C* cf = fc + ri.frow * Fp + fb + s;
+        xq[u] = (ok && q <= mmax) ? gload(cf + q * Fp) : C{0, 0};
+        xr[u] = (ok && q >= 1 && q2 <= mmax) ? gload(cf + q2 * Fp) : C{0, 0};
+        pq[u] = ok ? gload(post + q) : C{1, 0};
+        cq[u] = (ok && blue) ? gload(chirp + q) : C{1, 0};
       }
-      buf[lds_ix(q)] = y;
+#pragma unroll
+      for (int u = 0; u < FFT_SWEEP; ++u) {
+        const int e = e0 + u * FFT_THREADS;
+        if (e < n) {
+          const int s = e & (G - 1), q = e >> gs;
+          C x = xq[u];
+          if (q == 0) x.y = 0;
+          const C xr_ = cconj(xr[u]);
+          const C sm = cadd(x, xr_);
+          const C t = cmul(cconj(pq[u]), csub(x, xr_));
+          C y = C{sm.x - t.y, -(sm.y + t.x)};  // conj(sm + i t); zero where nothing was loaded
+          if (blue) y = cmul(y, cq[u]);
+          buf[s * S + lds_ix(q)] = y;
+        }
+      }
     }
     __syncthreads();
-    dft_h<T>(buf, cl, rad, tabs);
-    T* g = grid + (int64_t)f * p.npts + ri.goff;
-    for (int t = threadIdx.x; t < h; t += FFT_THREADS) {
-      const C y = buf[lds_ix(t)];
-      g[2 * t] = y.x;
-      g[2 * t + 1] = -y.y;
+    dft_h<T>(buf + sub * S, cl, rad, tabs, lt, nt);
+    const int f = fb + sub;
+    if (f < fend) {
+      // ring offsets and lengths are even, so (g_{2t}, g_{2t+1}) is one aligned pair
+      C* g = (C*)(grid + (int64_t)f * p.npts + ri.goff);
+      const C* src = buf + sub * S;
+      for (int t = lt; t < h; t += nt) {
+        const C y = src[lds_ix(t)];
+        gstore(g + t, C{y.x, -y.y});
+      }
     }
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Analysis: north ring j and its mirror, one field of the chunk [f0, f0 + FFT_FCHUNK).
+// Analysis: north ring j and its mirror, the fields [f0, fend) side by side.
 //   Z = DFT_h(z),  X_m = (Z_m + conj Z_{h-m})/2 - (i/2) w^{-m} (Z_m - conj Z_{h-m}),
 //   chat_m = X_m / n;  S = w_j (chat_N + chat_S),  A = w_j (chat_N - chat_S).
+// The north result waits in LDS (G (mmax + 1) values after the transform
+// buffers) while the mirror ring is transformed; the output step writes
+// element e as (m = e / G, s = e mod G) so that neighbouring lanes write
+// neighbouring fields of one Fourier row.
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__device__ __forceinline__ void analysis_field(const DevPlan& p, int ring, int f, const T* __restrict__ grid,
-                                               T* __restrict__ four) {
+__device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int fb, int fend,
+                                               const T* __restrict__ grid, T* __restrict__ four) {
   typedef typename V2T<T>::type C;
   extern __shared__ __align__(16) unsigned char smem[];
-  const RingInfo rn = p.rings[ring];
-  const RingInfo rs = p.rings[rn.mirror];
-  const FftClass cl = p.classes[rn.cls];
+  const RingInfo rn = gload(p.rings + ring);
+  const RingInfo rs = gload(p.rings + rn.mirror);
+  const FftClass cl = gload(p.classes + rn.cls);
   const int32_t* rad = p.classes[rn.cls].rad;
   const C* tabs = (const C*)p.fft;
+  const int h = cl.h, mmax = rn.mmax, L = cl.L;
+  const int gs = cl.gshift, G = 1 << gs;
   C* buf = (C*)smem;
-  C* keep = buf + lds_ix(cl.L) + 1;
+  const int S = lds_span(L);
+  C* keep = buf + G * S;
   const C* post = tabs + cl.post_off;
   const C* chirp = tabs + cl.chirp_off;
   C* fc = (C*)four;
-  const int h = cl.h, mmax = rn.mmax, L = cl.L;
   const bool blue = cl.bluestein;
-  const T scale = (T)(p.w[ring] / (double)rn.nlon);
+  const T scale = (T)(gload(p.w + ring) / (double)rn.nlon);
+  const int nt = FFT_THREADS >> gs;
+  const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
+  const int Q = blue ? L : h;
+  const int M = mmax + 1;
   {
+    const int f = fb + sub;
     for (int side = 0; side < 2; ++side) {
-      const T* g = grid + (int64_t)f * p.npts + (side ? rs.goff : rn.goff);
-      for (int t = threadIdx.x; t < (blue ? L : h); t += FFT_THREADS) {
-        C z = C{0, 0};
-        if (t < h) {
-          z = C{g[2 * t], g[2 * t + 1]};
-          if (blue) z = cmul(z, chirp[t]);
+      C* dst = buf + sub * S;
+      const C* g = (const C*)(grid + (int64_t)min(f, fend - 1) * p.npts + (side ? rs.goff : rn.goff));
+      for (int t0 = lt; t0 < Q; t0 += FFT_SWEEP * nt) {
+        C z[FFT_SWEEP], c[FFT_SWEEP];
+#pragma unroll
+        for (int u = 0; u < FFT_SWEEP; ++u) {
+          const int t = t0 + u * nt;
+          const bool ok = t < h && f < fend;
+          z[u] = ok ? gload(g + t) : C{0, 0};
+          c[u] = (ok && blue) ? gload(chirp + t) : C{1, 0};
         }
-        buf[lds_ix(t)] = z;
+#pragma unroll
+        for (int u = 0; u < FFT_SWEEP; ++u) {
+          const int t = t0 + u * nt;
+          if (t < Q) dst[lds_ix(t)] = blue ? cmul(z[u], c[u]) : z[u];
+        }
       }
       __syncthreads();
-      dft_h<T>(buf, cl, rad, tabs);
-      for (int m = threadIdx.x; m <= mmax; m += FFT_THREADS) {
-        const C zm = buf[lds_ix(m)];
-        const C zr = cconj(buf[lds_ix(m == 0 ? 0 : h - m)]);
-        const C s = cadd(zm, zr);
-        const C d = csub(zm, zr);
-        const C t = cmul(post[m], d);
-        // X = s/2 - (i/2) t
-        C x = C{(T)0.5 * (s.x + t.y), (T)0.5 * (s.y - t.x)};
-        if (m == 0) x = C{zm.x + zm.y, 0};
-        x = cscale(x, scale);
-        if (side == 0) {
-          keep[m] = x;
-        } else {
-          const C xn = keep[m];
-          C* row = fc + ((rn.frow + m) * 2) * (int64_t)p.Fp + f;
-          row[0] = cadd(xn, x);
-          row[p.Fp] = csub(xn, x);
+      dft_h<T>(dst, cl, rad, tabs, lt, nt);
+      const int nm = M << gs;
+      for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * FFT_THREADS) {
+        C pm[FFT_SWEEP];
+#pragma unroll
+        for (int u = 0; u < FFT_SWEEP; ++u) {
+          const int e = e0 + u * FFT_THREADS;
+          pm[u] = e < nm ? gload(post + (e >> gs)) : C{0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < FFT_SWEEP; ++u) {
+          const int e = e0 + u * FFT_THREADS;
+          if (e >= nm) continue;
+          const int s = e & (G - 1), m = e >> gs;
+          const C* z = buf + s * S;
+          const C zm = z[lds_ix(m)];
+          const C zr = cconj(z[lds_ix(m == 0 ? 0 : h - m)]);
+          const C sm = cadd(zm, zr);
+          const C d = csub(zm, zr);
+          const C t = cmul(pm[u], d);
+          // X = sm/2 - (i/2) t
+          C x = C{(T)0.5 * (sm.x + t.y), (T)0.5 * (sm.y - t.x)};
+          if (m == 0) x = C{zm.x + zm.y, 0};
+          x = cscale(x, scale);
+          if (side == 0) {
+            keep[s * M + m] = x;
+          } else if (fb + s < fend) {
+            const C xn = keep[s * M + m];
+            C* row = fc + ((rn.frow + m) * 2) * (int64_t)p.Fp + fb + s;
+            gstore(row, cadd(xn, x));
+            gstore(row + p.Fp, csub(xn, x));
+          }
         }
       }
       __syncthreads();
@@ -394,45 +538,42 @@ __device__ __forceinline__ void analysis_field(const DevPlan& p, int ring, int f
   }
 }
 
-size_t fft_lds_bytes(int prec, int L, int mmax) {
+size_t fft_lds_bytes(int prec, int L, int mmax, int G) {
   const size_t c = (prec == SHT_FP64) ? 16 : 8;
-  const size_t padded = (size_t)L + 1;
-  return c * (padded + (mmax >= 0 ? (size_t)mmax + 1 : 0));
+  return c * (size_t)G * ((size_t)lds_span(L) + (mmax >= 0 ? (size_t)mmax + 1 : 0));
 }
 
-// Kernels: work groups loop over virtual block ids (grid stride) so that a
-// launch of any size keeps the XCD grouping of decode_block.
+// Kernels: work groups loop over the items (grid stride).  FP32 kernels are
+// held to 128 VGPRs so that two 512-thread work groups share a CU (4 waves
+// per SIMD); FP64 ones need twice the registers and get 2 waves per SIMD.
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void fourier_synthesis_kernel(const DevPlan* __restrict__ plans,
+struct FftWaves {
+  static constexpr int value = sizeof(T) == 4 ? 4 : 2;
+};
+
+template <typename T>
+__global__ __launch_bounds__(FFT_THREADS, FftWaves<T>::value) void fourier_synthesis_kernel(const DevPlan* __restrict__ plans,
                                                                         const FftItem* __restrict__ items, int nitems,
                                                                         const IoBind* __restrict__ io, IoBind io0) {
-  const int nvirt = (int)fft_grid_blocks_dev(nitems);
-  for (int v = blockIdx.x; v < nvirt; v += gridDim.x) {
-    int item, slot;
-    if (!decode_block(v, nitems, &item, &slot)) continue;
-    const FftItem it = items[item];
-    const DevPlan p = plans[it.plan];
-    const int f = it.f0 + slot;
-    if (f >= p.F) continue;
-    const IoBind b = io ? io[it.plan] : io0;
-    synthesis_field<T>(p, it.ring, f, (const T*)b.ws, (T*)b.grid);
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const FftItem it = gload(items + w);
+    if (it.ring < 0) continue;
+    const DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
+    synthesis_group<T>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid);
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(FFT_THREADS) void fourier_analysis_kernel(const DevPlan* __restrict__ plans,
+__global__ __launch_bounds__(FFT_THREADS, FftWaves<T>::value) void fourier_analysis_kernel(const DevPlan* __restrict__ plans,
                                                                        const FftItem* __restrict__ items, int nitems,
                                                                        const IoBind* __restrict__ io, IoBind io0) {
-  const int nvirt = (int)fft_grid_blocks_dev(nitems);
-  for (int v = blockIdx.x; v < nvirt; v += gridDim.x) {
-    int item, slot;
-    if (!decode_block(v, nitems, &item, &slot)) continue;
-    const FftItem it = items[item];
-    const DevPlan p = plans[it.plan];
-    const int f = it.f0 + slot;
-    if (f >= p.F) continue;
-    const IoBind b = io ? io[it.plan] : io0;
-    analysis_field<T>(p, it.ring, f, (const T*)b.grid, (T*)b.ws);
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const FftItem it = gload(items + w);
+    if (it.ring < 0) continue;
+    const DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
+    analysis_group<T>(p, it.ring, it.f0, it.fend, (const T*)b.grid, (T*)b.ws);
   }
 }
 

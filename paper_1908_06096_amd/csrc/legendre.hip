@@ -99,7 +99,7 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
   __shared__ T As[2][KI][BM + LDS_PAD];
   __shared__ T Bs[2][KI][BN + LDS_PAD];
 
-  const MInfo mi = p.ms[it.m];
+  const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -142,13 +142,13 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
       const bool ok = a_ok[a] && (kc * NC + a_ch[a] < a_nch[a]);
       const V* src = (const V*)(tab + a_base[a] + kc * a_step);
 #pragma unroll
-      for (int v = 0; v < KCH / VN; ++v) ra[a][v] = ok ? src[v] : V{};
+      for (int v = 0; v < KCH / VN; ++v) ra[a][v] = ok ? gload(src + v) : V{};
     }
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int d = 2 * KI * kc + q + TPF * j;  // n - m
       C2 x = C2{};
-      if (f_ok && m + d <= p.N) x = sp[d];
+      if (f_ok && m + d <= p.N) x = gload(sp + d);
       if (m == 0) x.y = 0;
       rb[j] = x;
     }
@@ -202,17 +202,17 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
     for (int e = 0; e < 4; ++e) {
       const int row = it.t0 + wr * WM + i * 16 + acc_row<T>(lane, e);
       if (row >= mi.L) continue;
-      const RingInfo rn = p.rings[mi.first_ring + row];
+      const RingInfo rn = gload(p.rings + mi.first_ring + row);
       T* dn = four + (rn.frow + m) * rowlen;
-      T* ds = four + (p.rings[rn.mirror].frow + m) * rowlen;
+      T* ds = four + (gload(p.rings + rn.mirror).frow + m) * rowlen;
 #pragma unroll
       for (int j = 0; j < IN; ++j) {
         const int col = it.c0 + wc * WN + j * 16 + (lane & 15);
         if (col < twoF) {
           const T S = acc[0][i][j][e];
           const T A = acc[1][i][j][e];
-          dn[col] = S + A;
-          ds[col] = S - A;
+          gstore(dn + col, S + A);
+          gstore(ds + col, S - A);
         }
       }
     }
@@ -248,7 +248,7 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
   __shared__ T Xs[2][KJ][BC + LDS_PAD];
   __shared__ T Ts[2][KJ][BK + LDS_PAD];
 
-  const MInfo mi = p.ms[it.m];
+  const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -293,8 +293,8 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
       V v = V{};
       const int c = it.c0 + x_c[a];
       if (r < mi.L && c < 2 * p.Fp && x_cok) {
-        const int64_t fr = p.rings[mi.first_ring + r].frow;
-        v = *(const V*)(four + ((fr + m) * 2 + x_par[a]) * rowlen + c);
+        const int64_t fr = gload(p.rings + mi.first_ring + r).frow;
+        v = gload((const V*)(four + ((fr + m) * 2 + x_par[a]) * rowlen + c));
       }
       rx[a] = v;
     }
@@ -302,7 +302,7 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
     for (int a = 0; a < TU; ++a) {
       const V* src = (const V*)(tab + t_base[a] + (int64_t)r0 * KCH);
 #pragma unroll
-      for (int v = 0; v < KCH / VN; ++v) rt[a][v] = t_ok[a] ? src[v] : V{};
+      for (int v = 0; v < KCH / VN; ++v) rt[a][v] = t_ok[a] ? gload(src + v) : V{};
     }
   };
 
@@ -360,7 +360,7 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
             if (c < twoF) {
               C2 v = C2{acc[par][i][j][e], acc[par][i][j][e + 1]};
               if (m == 0) v.y = 0;
-              dst[(int64_t)(c >> 1) * p.nspec] = v;
+              gstore(dst + (int64_t)(c >> 1) * p.nspec, v);
             }
           }
         } else {
@@ -370,7 +370,7 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
             if (c < twoF) {
               T v = acc[par][i][j][e];
               if (m == 0 && (c & 1)) v = 0;
-              ((T*)(dst + (int64_t)(c >> 1) * p.nspec))[c & 1] = v;
+              gstore((T*)(dst + (int64_t)(c >> 1) * p.nspec) + (c & 1), v);
             }
           }
         }
@@ -427,7 +427,7 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
   __shared__ __align__(16) u16 As[2][2][BM][KI + BPAD];  // [plane][parity][row][k]
   __shared__ __align__(16) u16 Bs[2][2][BN][KI + BPAD];  // [plane][parity][col][k]
 
-  const MInfo mi = p.ms[it.m];
+  const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -467,13 +467,13 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
 #pragma unroll
     for (int a = 0; a < AU; ++a) {
       const bool ok = a_ok[a] && (kc * NC + a_ch[a] < a_nch[a]);
-      ra[a] = ok ? *(const uint4*)(tab + a_base[a] + kc * a_step) : make_uint4(0, 0, 0, 0);
+      ra[a] = ok ? gload((const uint4*)(tab + a_base[a] + kc * a_step)) : make_uint4(0, 0, 0, 0);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int d = 2 * KI * kc + 16 * q + i;
       float2 x = make_float2(0.f, 0.f);
-      if (f_ok && m + d <= p.N) x = sp[d];
+      if (f_ok && m + d <= p.N) x = gload(sp + d);
       if (m == 0) x.y = 0.f;
       rb[i] = x;
     }
@@ -542,17 +542,17 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
     for (int e = 0; e < 4; ++e) {
       const int row = it.t0 + wr * WM + i * 16 + 4 * (lane >> 4) + e;
       if (row >= mi.L) continue;
-      const RingInfo rn = p.rings[mi.first_ring + row];
+      const RingInfo rn = gload(p.rings + mi.first_ring + row);
       float* dn = four + (rn.frow + m) * rowlen;
-      float* ds = four + (p.rings[rn.mirror].frow + m) * rowlen;
+      float* ds = four + (gload(p.rings + rn.mirror).frow + m) * rowlen;
 #pragma unroll
       for (int j = 0; j < IN; ++j) {
         const int col = it.c0 + wc * WN + j * 16 + (lane & 15);
         if (col < twoF) {
           const float S = acc[0][i][j][e];
           const float A = acc[1][i][j][e];
-          dn[col] = S + A;
-          ds[col] = S - A;
+          gstore(dn + col, S + A);
+          gstore(ds + col, S - A);
         }
       }
     }
@@ -577,7 +577,7 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   __shared__ __align__(16) u16 Xs[2][2][BC][KJ + BPAD];  // [plane][parity][col c][ring]
   __shared__ __align__(16) u16 Ts[2][2][BK][KJ + BPAD];  // [plane][parity][k][ring]
 
-  const MInfo mi = p.ms[it.m];
+  const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -611,8 +611,8 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
       const int r = r0 + e;
       float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
       if (r < mi.L && x_c < 2 * p.Fp) {
-        const int64_t fr = p.rings[mi.first_ring + r].frow;
-        v = *(const float4*)(four + ((fr + m) * 2 + x_par) * rowlen + x_c);
+        const int64_t fr = gload(p.rings + mi.first_ring + r).frow;
+        v = gload((const float4*)(four + ((fr + m) * 2 + x_par) * rowlen + x_c));
       }
       rx[e] = v;
     }
@@ -620,7 +620,7 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int r = t0 + e;
-      rt[e] = (t_ok && r < mi.Lp) ? *(const uint4*)(tab + t_base + (int64_t)r * KCH) : make_uint4(0, 0, 0, 0);
+      rt[e] = (t_ok && r < mi.Lp) ? gload((const uint4*)(tab + t_base + (int64_t)r * KCH)) : make_uint4(0, 0, 0, 0);
     }
   };
 
@@ -709,7 +709,7 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
           if (c < twoF) {
             float2 v = make_float2(acc[par][i][j][e], acc[par][i][j][e + 1]);
             if (m == 0) v.y = 0.f;
-            dst[(int64_t)(c >> 1) * p.nspec] = v;
+            gstore(dst + (int64_t)(c >> 1) * p.nspec, v);
           }
         }
       }
@@ -727,9 +727,9 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(const DevPlan*
                                                                const WorkItem* __restrict__ items, int nitems,
                                                                const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const DevPlan p = plans[it.plan];
-    const IoBind b = io ? io[it.plan] : io0;
+    const WorkItem it = gload(items + w);
+    const DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
     inverse_tile<T, BM, BN, KI, WCOL>(p, it, (const T*)b.spec, (T*)b.ws);
   }
 }
@@ -739,9 +739,9 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(const DevPlan* 
                                                               const WorkItem* __restrict__ items, int nitems,
                                                               const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const DevPlan p = plans[it.plan];
-    const IoBind b = io ? io[it.plan] : io0;
+    const WorkItem it = gload(items + w);
+    const DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
     direct_tile<T, BC, BK, KJ, WKW>(p, it, (const T*)b.ws, (T*)b.spec);
   }
 }
@@ -751,9 +751,9 @@ __global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(const DevP
                                                                       const WorkItem* __restrict__ items, int nitems,
                                                                       const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const DevPlan p = plans[it.plan];
-    const IoBind b = io ? io[it.plan] : io0;
+    const WorkItem it = gload(items + w);
+    const DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
     inverse_bf16x3_tile<BM, BN>(p, it, (const float*)b.spec, (float*)b.ws);
   }
 }
@@ -763,9 +763,9 @@ __global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(const DevPl
                                                                      const WorkItem* __restrict__ items, int nitems,
                                                                      const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
-    const WorkItem it = items[w];
-    const DevPlan p = plans[it.plan];
-    const IoBind b = io ? io[it.plan] : io0;
+    const WorkItem it = gload(items + w);
+    const DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
     direct_bf16x3_tile<BC, BK>(p, it, (const float*)b.ws, (float*)b.spec);
   }
 }

@@ -25,9 +25,55 @@ constexpr int FPAD = 16;
 
 // FFT: threads per work group and complex values each thread may hold in
 // registers during one pass; together they bound the transform length.
+// A work group takes FFT_FCHUNK fields of one ring, G of them at a time.
 constexpr int FFT_THREADS = 512;
-constexpr int FFT_REGS = 18;
+constexpr int FFT_REGS = 20;
 constexpr int FFT_MAX_RADICES = 20;
+constexpr int FFT_FCHUNK = 16;
+constexpr int FFT_MAX_G = 8;
+
+// Device-memory accesses through address-space-1 pointers.  Pointers read
+// out of plan structures are generic, and generic (FLAT) accesses count
+// against the LDS wait counter as well as the memory one, so every wait for
+// an LDS read would also wait for loads still in flight; these helpers make
+// the compiler emit global_load / global_store instead.
+// HIP's float2 / double2 are classes whose copy constructor takes a generic
+// reference, which would drop the address space again, so 8- and 16-byte
+// values move as native clang vectors of 32-bit words.
+#define SHT_GLOBAL __attribute__((address_space(1)))
+typedef uint32_t gword2 __attribute__((ext_vector_type(2)));
+typedef uint32_t gword4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ T gload(const T* p) {
+  if constexpr (sizeof(T) == 8 && alignof(T) >= 8) {
+    const gword2 w = *(const SHT_GLOBAL gword2*)p;
+    return __builtin_bit_cast(T, w);
+  } else if constexpr (sizeof(T) == 16 && alignof(T) >= 16) {
+    const gword4 w = *(const SHT_GLOBAL gword4*)p;
+    return __builtin_bit_cast(T, w);
+  } else if constexpr (!__is_arithmetic(T) && sizeof(T) % 4 == 0) {
+    // metadata structures: word by word (uniform addresses become scalar loads)
+    struct Words {
+      uint32_t w[sizeof(T) / 4];
+    } u;
+    const SHT_GLOBAL uint32_t* q = (const SHT_GLOBAL uint32_t*)p;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) u.w[i] = q[i];
+    return __builtin_bit_cast(T, u);
+  } else {
+    return *(const SHT_GLOBAL T*)p;
+  }
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T* p, const T& v) {
+  if constexpr (sizeof(T) == 8 && alignof(T) >= 8) {
+    *(SHT_GLOBAL gword2*)p = __builtin_bit_cast(gword2, v);
+  } else if constexpr (sizeof(T) == 16 && alignof(T) >= 16) {
+    *(SHT_GLOBAL gword4*)p = __builtin_bit_cast(gword4, v);
+  } else {
+    *(SHT_GLOBAL T*)p = v;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Device metadata
@@ -52,6 +98,8 @@ struct FftClass {
   int32_t bluestein;
   int32_t nrad;
   int32_t rad[FFT_MAX_RADICES];
+  int32_t G;          // fields transformed side by side per round (power of two)
+  int32_t gshift;     // log2 G; each field gets FFT_THREADS / G threads
   int64_t root_off;   // L - 1 twiddles, pass after pass: exp(-2 pi i r k / (Ns R)) at
                       // k (R - 1) + r - 1 of the pass table (k < Ns, 1 <= r < R)
   int64_t post_off;   // h complex values exp(-2 pi i q / (2h))
@@ -80,12 +128,14 @@ struct WorkItem {
   int32_t plan;
 };
 
-// An FFT work item: a ring (a north ring for analysis) and a chunk of fields.
+// An FFT work item: a ring (a north ring for analysis) and the fields
+// [f0, fend) transformed side by side (at most the class's G); ring < 0
+// marks an empty slot of the work list.
 struct FftItem {
   int32_t ring;
   int32_t f0;
   int32_t plan;
-  int32_t pad;
+  int32_t fend;
 };
 
 // Device buffers of one transform: spectral [F][nspec] complex, grid
@@ -149,7 +199,7 @@ hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, const FftIte
 hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
                                    const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s);
 hipError_t fft_set_max_lds(size_t bytes);
-size_t fft_lds_bytes(int prec, int L, int mmax);
+size_t fft_lds_bytes(int prec, int L, int mmax, int G);
 size_t fft_grid_blocks(int nitems);
 int fft_blocks_per_cu(int prec, size_t lds);
 
