@@ -242,7 +242,7 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
 }
 
 // What the last pass of a transform does with its outputs.
-enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2 };
+enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2, OUT_GRID = 3, OUT_GRID_CHIRP = 4 };
 
 // One Stockham pass of radix R over L points in LDS, after Ns points have
 // been combined, carried out by the nt threads (thread lt) that own this
@@ -251,14 +251,18 @@ enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2 };
 // (b mod Ns)(R - 1) + r - 1, so lanes with consecutive b read consecutive
 // entries) and writes y[(b / Ns) Ns R + b mod Ns + r Ns].  All reads of the
 // pass land in registers before the barrier, so one LDS buffer suffices.
-// OUT_KHAT stores conj(y khat) and OUT_CHIRP stores c_q conj(y_q) for q < h
-// (the element-wise steps of the chirp-z convolution).  Each instantiation
-// is its own non-inlined function so that its registers are allocated for
-// it alone.  Every thread of the work group calls it (the barriers).
+//   OUT_KHAT stores conj(y khat), OUT_CHIRP stores c_q conj(y_q) for q < h
+//     (the element-wise steps of the chirp-z convolution);
+//   OUT_GRID writes conj(y_q) and OUT_GRID_CHIRP writes conj(c_q) y_q, the
+//     conjugate of what OUT_PLAIN and OUT_CHIRP would store, for q < h to
+//     io in device memory (nothing when io is null).
+// Each instantiation is its own non-inlined function so that its registers
+// are allocated for it alone.  Every thread of the work group calls it (the
+// barriers).
 template <typename T, int R, int MODE>
 __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
-                                           int h, int lt, int nt) {
+                                           typename V2T<T>::type* io, int h, int lt, int nt) {
   typedef typename V2T<T>::type C;
   constexpr int MAXB = FFT_REGS / R;
   const int nb = L / R;
@@ -296,8 +300,12 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
           buf[lds_ix(o)] = v[i][r];
         } else if constexpr (MODE == OUT_KHAT) {
           buf[lds_ix(o)] = cconj(cmul(v[i][r], gload(aux + o)));
-        } else {
+        } else if constexpr (MODE == OUT_CHIRP) {
           if (o < h) buf[lds_ix(o)] = cmul(gload(aux + o), cconj(v[i][r]));
+        } else if constexpr (MODE == OUT_GRID) {
+          if (io && o < h) gstore(io + o, cconj(v[i][r]));
+        } else {
+          if (io && o < h) gstore(io + o, cmul(cconj(gload(aux + o)), v[i][r]));
         }
       }
     }
@@ -306,56 +314,60 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
 }
 
 template <typename T, int MODE>
-__device__ inline void pass_dispatch(int R, typename V2T<T>::type* buf, int L, int Ns,
-                                     const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h,
-                                     int lt, int nt) {
+__device__ __forceinline__ void pass_dispatch(int R, typename V2T<T>::type* buf, int L, int Ns,
+                                     const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
+                                     typename V2T<T>::type* io, int h, int lt, int nt) {
+#define SHT_PASS(RR) stockham_pass<T, RR, MODE>(buf, L, Ns, tw, aux, io, h, lt, nt)
   switch (R) {
-    case 20: stockham_pass<T, 20, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 18: stockham_pass<T, 18, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 16: stockham_pass<T, 16, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 15: stockham_pass<T, 15, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 12: stockham_pass<T, 12, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 10: stockham_pass<T, 10, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 6: stockham_pass<T, 6, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 9: stockham_pass<T, 9, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 8: stockham_pass<T, 8, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 5: stockham_pass<T, 5, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 4: stockham_pass<T, 4, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    case 3: stockham_pass<T, 3, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
-    default: stockham_pass<T, 2, MODE>(buf, L, Ns, tw, aux, h, lt, nt); break;
+    case 20: SHT_PASS(20); break;
+    case 18: SHT_PASS(18); break;
+    case 16: SHT_PASS(16); break;
+    case 15: SHT_PASS(15); break;
+    case 12: SHT_PASS(12); break;
+    case 10: SHT_PASS(10); break;
+    case 9: SHT_PASS(9); break;
+    case 8: SHT_PASS(8); break;
+    case 6: SHT_PASS(6); break;
+    case 5: SHT_PASS(5); break;
+    case 4: SHT_PASS(4); break;
+    case 3: SHT_PASS(3); break;
+    default: SHT_PASS(2); break;
   }
+#undef SHT_PASS
 }
 
 // Forward DFT of L points held in LDS (natural order in and out); the last
-// pass applies MODE.
+// pass applies MODE with aux and io.
 template <typename T, int MODE>
-__device__ void fft_lds(typename V2T<T>::type* buf, int L, int nrad, const int32_t* rad,
-                        const typename V2T<T>::type* tw, const typename V2T<T>::type* aux, int h, int lt, int nt) {
+__device__ __forceinline__ void fft_lds(typename V2T<T>::type* buf, int L, int nrad, const int32_t* rad,
+                                        const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
+                                        typename V2T<T>::type* io, int h, int lt, int nt) {
   int Ns = 1;
   for (int q = 0; q < nrad; ++q) {
     const int R = gload(rad + q);
-    if (q == nrad - 1) pass_dispatch<T, MODE>(R, buf, L, Ns, tw, aux, h, lt, nt);
-    else pass_dispatch<T, OUT_PLAIN>(R, buf, L, Ns, tw, aux, h, lt, nt);
+    if (q == nrad - 1) pass_dispatch<T, MODE>(R, buf, L, Ns, tw, aux, io, h, lt, nt);
+    else pass_dispatch<T, OUT_PLAIN>(R, buf, L, Ns, tw, nullptr, nullptr, h, lt, nt);
     tw += Ns * (R - 1);
     Ns *= R;
   }
 }
 
-// Forward complex DFT of length h.  On entry buf[lds_ix(t)] holds z_t,
-// t < h, already multiplied by the chirp c_t for chirp-z classes, whose
-// entries h <= t < L must be zero.  On exit buf[lds_ix(q)], q < h, holds
-// Z_q.  Chirp-z:
-// A = DFT_L(a), B = conj(A khat), Z_q = c_q conj(DFT_L(B))_q.
-template <typename T>
-__device__ void dft_h(typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
-                      const typename V2T<T>::type* tabs, int lt, int nt) {
+// Forward complex DFT of length h.  Input: z_t, t < h, in LDS at
+// buf[lds_ix(t)], multiplied by the chirp c_t for chirp-z classes, whose
+// entries h <= t < L must be zero.  Output: Z_q, q < h, in LDS at
+// buf[lds_ix(q)], or with GRID_OUT its conjugate written to io (nothing
+// when io is null).  Chirp-z: A = DFT_L(a), B = conj(A khat),
+// Z_q = c_q conj(DFT_L(B))_q.
+template <typename T, bool GRID_OUT>
+__device__ __forceinline__ void dft_h(typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
+                      const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
   if (!c.bluestein) {
-    fft_lds<T, OUT_PLAIN>(buf, c.L, c.nrad, rad, tw, nullptr, c.h, lt, nt);
+    fft_lds<T, GRID_OUT ? OUT_GRID : OUT_PLAIN>(buf, c.L, c.nrad, rad, tw, nullptr, io, c.h, lt, nt);
     return;
   }
-  fft_lds<T, OUT_KHAT>(buf, c.L, c.nrad, rad, tw, tabs + c.khat_off, c.h, lt, nt);
-  fft_lds<T, OUT_CHIRP>(buf, c.L, c.nrad, rad, tw, tabs + c.chirp_off, c.h, lt, nt);
+  fft_lds<T, OUT_KHAT>(buf, c.L, c.nrad, rad, tw, tabs + c.khat_off, nullptr, c.h, lt, nt);
+  fft_lds<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP>(buf, c.L, c.nrad, rad, tw, tabs + c.chirp_off, io, c.h, lt, nt);
 }
 
 // Sweeps over a ring (gathers, scatters) issue the global loads of
@@ -429,18 +441,11 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
       }
     }
     __syncthreads();
-    dft_h<T>(buf + sub * S, cl, rad, tabs, lt, nt);
+    // ring offsets and lengths are even, so (g_{2t}, g_{2t+1}) is one aligned pair
     const int f = fb + sub;
-    if (f < fend) {
-      // ring offsets and lengths are even, so (g_{2t}, g_{2t+1}) is one aligned pair
-      C* g = (C*)(grid + (int64_t)f * p.npts + ri.goff);
-      const C* src = buf + sub * S;
-      for (int t = lt; t < h; t += nt) {
-        const C y = src[lds_ix(t)];
-        gstore(g + t, C{y.x, -y.y});
-      }
-    }
-    __syncthreads();
+    C* g = f < fend ? (C*)(grid + (int64_t)f * p.npts + ri.goff) : nullptr;
+    // the last pass writes the grid (the conjugate of the inverse transform)
+    dft_h<T, true>(buf + sub * S, cl, rad, tabs, g, lt, nt);
   }
 }
 
@@ -499,7 +504,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
         }
       }
       __syncthreads();
-      dft_h<T>(dst, cl, rad, tabs, lt, nt);
+      dft_h<T, false>(dst, cl, rad, tabs, nullptr, lt, nt);
       const int nm = M << gs;
       for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * FFT_THREADS) {
         C pm[FFT_SWEEP];
