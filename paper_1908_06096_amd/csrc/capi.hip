@@ -181,8 +181,8 @@ struct sht_plan_s {
 namespace {
 
 // Legendre work items of one plan for a tile variant, tagged with `plan`.
-void legendre_items(const sht_plan_s* p, int variant, int plan, std::vector<WorkItem>* inv,
-                    std::vector<WorkItem>* dir) {
+void legendre_items_raw(const sht_plan_s* p, int variant, int plan, std::vector<WorkItem>* inv,
+                        std::vector<WorkItem>* dir) {
   int ir, ic, dr, dc;
   legendre_tiles(p->prec, variant, &ir, &ic, &dr, &dc);
   const int twoF = 2 * p->F;
@@ -194,6 +194,44 @@ void legendre_items(const sht_plan_s* p, int variant, int plan, std::vector<Work
     for (int t0 = 0; t0 < kmax; t0 += dr)
       for (int c0 = 0; c0 < twoF; c0 += dc) dir->push_back(WorkItem{mi.m, t0, c0, plan});
   }
+}
+
+// Work groups go to the XCDs round-robin by id.  Tiles that share an
+// operand slice (same plan, m and row tile t0: the synthesis table rows, or
+// the analysis table columns) are given ids congruent modulo NUM_XCD, 8 such
+// groups side by side, so that they run on one XCD at the same time and read
+// the slice through its L2 once.  Empty slots (m = -1) pad a group shorter
+// than the others of its eight.  Input: items of one group consecutive.
+constexpr int NUM_XCD = 8;
+
+void legendre_arrange(std::vector<WorkItem>* items) {
+  std::vector<WorkItem> in;
+  in.swap(*items);
+  size_t i = 0;
+  while (i < in.size()) {
+    size_t start[NUM_XCD], len[NUM_XCD], most = 0;
+    int ng = 0;
+    while (ng < NUM_XCD && i < in.size()) {
+      size_t j = i;
+      while (j < in.size() && in[j].plan == in[i].plan && in[j].m == in[i].m && in[j].t0 == in[i].t0) ++j;
+      start[ng] = i;
+      len[ng] = j - i;
+      most = std::max(most, len[ng]);
+      ++ng;
+      i = j;
+    }
+    for (size_t r = 0; r < most; ++r)
+      for (int g = 0; g < NUM_XCD; ++g)
+        items->push_back(g < ng && r < len[g] ? in[start[g] + r] : WorkItem{-1, 0, 0, 0});
+  }
+}
+
+// Arranged work lists of one plan.
+void legendre_items(const sht_plan_s* p, int variant, int plan, std::vector<WorkItem>* inv,
+                    std::vector<WorkItem>* dir) {
+  legendre_items_raw(p, variant, plan, inv, dir);
+  legendre_arrange(inv);
+  legendre_arrange(dir);
 }
 
 // FFT work items of one plan, longest transforms first.
@@ -219,8 +257,6 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
 // of its eight): they run on one XCD at the same time, and their strided
 // reads and writes of the chunk's Fourier rows (fields are the innermost
 // index) meet in that XCD's L2.
-constexpr int NUM_XCD = 8;
-
 void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
   std::vector<FftItem> chunks;
   chunks.swap(*items);
@@ -571,7 +607,7 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
   b->syn.clear();
   b->ana.clear();
   for (int i = 0; i < b->n; ++i) {
-    legendre_items(b->plans[i], b->variant[i], i, &b->inv[b->variant[i]], &b->dir[b->variant[i]]);
+    legendre_items_raw(b->plans[i], b->variant[i], i, &b->inv[b->variant[i]], &b->dir[b->variant[i]]);
     fft_items(b->plans[i], i, &b->syn, &b->ana);
   }
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
@@ -579,6 +615,8 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
                      [&](const WorkItem& x, const WorkItem& y) { return inv_cost(b, x) > inv_cost(b, y); });
     std::stable_sort(b->dir[v].begin(), b->dir[v].end(),
                      [&](const WorkItem& x, const WorkItem& y) { return dir_cost(b, x) > dir_cost(b, y); });
+    legendre_arrange(&b->inv[v]);
+    legendre_arrange(&b->dir[v]);
   }
   std::stable_sort(b->syn.begin(), b->syn.end(),
                    [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });

@@ -398,18 +398,20 @@ __device__ inline f32x4 mfma_bf16(const uint4& a, const uint4& b, f32x4 c) {
                                                  0, 0, 0);
 }
 
-__device__ inline u16 bf16_bits(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (u16)(u >> 16);
-}
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
 
-__device__ inline void split_bf16(float x, u16* hi, u16* lo) {
-  *hi = bf16_bits(x);
-  *lo = bf16_bits(x - __uint_as_float(((uint32_t)*hi) << 16));
+// Split of two floats a, b: words holding (hi_a, hi_b) and (lo_a, lo_b),
+// element a in the low half.  The conversions round to nearest even (one
+// v_cvt_pk_bf16_f32 each); hi is widened back exactly by a shift.
+__device__ inline void split2_bf16(float a, float b, uint32_t* hi, uint32_t* lo) {
+  const f32x2v x = {a, b};
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(x, bf16x2v));
+  const float ha = __uint_as_float(h << 16), hb = __uint_as_float(h & 0xffff0000u);
+  const f32x2v r = {a - ha, b - hb};
+  *hi = h;
+  *lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(r, bf16x2v));
 }
-
-__device__ inline uint32_t pack2(u16 a, u16 b) { return (uint32_t)a | ((uint32_t)b << 16); }
 
 constexpr int BPAD = 8;
 
@@ -496,13 +498,14 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
     for (int par = 0; par < 2; ++par) {
 #pragma unroll
       for (int comp = 0; comp < 2; ++comp) {
-        u16 h[8], l[8];
+        uint32_t h[4], l[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) split_bf16(comp ? rb[2 * e + par].y : rb[2 * e + par].x, &h[e], &l[e]);
-        *(uint4*)&Bs[0][par][2 * fi + comp][8 * q] =
-            make_uint4(pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7]));
-        *(uint4*)&Bs[1][par][2 * fi + comp][8 * q] =
-            make_uint4(pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7]));
+        for (int e = 0; e < 4; ++e) {
+          const float2 u = rb[4 * e + par], w = rb[4 * e + 2 + par];
+          split2_bf16(comp ? u.y : u.x, comp ? w.y : w.x, &h[e], &l[e]);
+        }
+        *(uint4*)&Bs[0][par][2 * fi + comp][8 * q] = make_uint4(h[0], h[1], h[2], h[3]);
+        *(uint4*)&Bs[1][par][2 * fi + comp][8 * q] = make_uint4(l[0], l[1], l[2], l[3]);
       }
     }
     __syncthreads();
@@ -637,16 +640,16 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
     // X: 4 columns x 8 rings -> per column 8 rings of hi and lo
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
-      u16 h[8], l[8];
+      uint32_t h[4], l[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float v = cc == 0 ? rx[e].x : cc == 1 ? rx[e].y : cc == 2 ? rx[e].z : rx[e].w;
-        split_bf16(v, &h[e], &l[e]);
+      for (int e = 0; e < 4; ++e) {
+        const float4 u = rx[2 * e], w = rx[2 * e + 1];
+        const float a = cc == 0 ? u.x : cc == 1 ? u.y : cc == 2 ? u.z : u.w;
+        const float b = cc == 0 ? w.x : cc == 1 ? w.y : cc == 2 ? w.z : w.w;
+        split2_bf16(a, b, &h[e], &l[e]);
       }
-      *(uint4*)&Xs[0][x_par][4 * x_cq + cc][8 * x_oct] =
-          make_uint4(pack2(h[0], h[1]), pack2(h[2], h[3]), pack2(h[4], h[5]), pack2(h[6], h[7]));
-      *(uint4*)&Xs[1][x_par][4 * x_cq + cc][8 * x_oct] =
-          make_uint4(pack2(l[0], l[1]), pack2(l[2], l[3]), pack2(l[4], l[5]), pack2(l[6], l[7]));
+      *(uint4*)&Xs[0][x_par][4 * x_cq + cc][8 * x_oct] = make_uint4(h[0], h[1], h[2], h[3]);
+      *(uint4*)&Xs[1][x_par][4 * x_cq + cc][8 * x_oct] = make_uint4(l[0], l[1], l[2], l[3]);
     }
     // table: 8 rings x 8 k (16-bit) -> 8 k x 8 rings
     {
@@ -728,6 +731,7 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(const DevPlan*
                                                                const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
+    if (it.m < 0) continue;  // empty slot of the work list
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     inverse_tile<T, BM, BN, KI, WCOL>(p, it, (const T*)b.spec, (T*)b.ws);
@@ -740,6 +744,7 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(const DevPlan* 
                                                               const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
+    if (it.m < 0) continue;  // empty slot of the work list
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     direct_tile<T, BC, BK, KJ, WKW>(p, it, (const T*)b.ws, (T*)b.spec);
@@ -752,6 +757,7 @@ __global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(const DevP
                                                                       const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
+    if (it.m < 0) continue;  // empty slot of the work list
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     inverse_bf16x3_tile<BM, BN>(p, it, (const float*)b.spec, (float*)b.ws);
@@ -764,6 +770,7 @@ __global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(const DevPl
                                                                      const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
+    if (it.m < 0) continue;  // empty slot of the work list
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     direct_bf16x3_tile<BC, BK>(p, it, (const float*)b.ws, (float*)b.spec);

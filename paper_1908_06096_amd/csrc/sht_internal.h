@@ -120,7 +120,7 @@ struct MInfo {
 
 // A Legendre work item: wavenumber, tile along the table rows or columns,
 // tile along the field columns, and the plan (index into the launch's plan
-// array) it belongs to.
+// array) it belongs to; m < 0 marks an empty slot of the work list.
 struct WorkItem {
   int32_t m;
   int32_t t0;  // first row (synthesis: ring row; analysis: k index)
