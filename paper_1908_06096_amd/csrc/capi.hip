@@ -125,7 +125,7 @@ int cu_count() {
 // covers them (wider tiles only waste MFMA work on padding columns).
 int default_variant(int prec, int F) {
   const int cols = 2 * F;
-  if (prec == SHT_BF16X3) return TILE_C128;
+  if (prec == SHT_BF16X3) return TILE_C64;
   if (cols <= 32) return TILE_C32;
   if (cols <= 64 || prec == SHT_FP64) return TILE_C64;
   return TILE_C128;

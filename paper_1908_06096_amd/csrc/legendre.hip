@@ -415,151 +415,191 @@ __device__ inline void split2_bf16(float a, float b, uint32_t* hi, uint32_t* lo)
 
 constexpr int BPAD = 8;
 
-template <int BM, int BN>
-__device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const WorkItem it,
-                                                    const float* __restrict__ spec, float* __restrict__ four) {
-  const int64_t plane = p.tab_plane;
-  constexpr int KI = 32;                  // k of each parity per iteration
-  constexpr int WM = BM / 2, WN = BN / 2;
-  constexpr int IM = WM / 16, IN = WN / 16;
-  constexpr int NC = KI / KCH;            // table chunks per parity per iteration
-  constexpr int AUNITS = 2 * 2 * NC * BM; // (plane, parity, chunk, row) units of 16 bytes
-  constexpr int AU = AUNITS / 256;
-  static_assert(BN / 2 * 4 == 256, "one thread per (field, quarter)");
-  __shared__ __align__(16) u16 As[2][2][BM][KI + BPAD];  // [plane][parity][row][k]
-  __shared__ __align__(16) u16 Bs[2][2][BN][KI + BPAD];  // [plane][parity][col][k]
+// Raw buffer descriptor over `bytes` bytes from `base` (no stride; loads
+// past the range return zero).
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Synthesis in BF16 split precision on a tile of 128 rings x 64 real
+// columns, both parities.  Wave w computes parity w >> 1 on the rows
+// [64 (w & 1), +64): a 64 x 64 block of 4 x 4 MFMA blocks, so that each
+// 16-byte operand read from LDS feeds four MFMAs per split term and the
+// four waves of a SIMD's work groups stay within the LDS rate.  The two
+// parities meet in the epilogue through LDS (the N/S fold needs S and A of
+// the same element).
+//
+// LDS operand layout [parity][plane][k chunk of 8][row or column] x 8 k:
+// a lane's operand (8 consecutive k of one row or column) is one 16-byte
+// read, and 8 lanes reading 8 consecutive rows touch distinct banks.
+// Table units (16 bytes: 8 k of one ring) and spectral values are loaded
+// without branches (clamped indices, zeros selected) one step ahead.
+constexpr int BF_BM = 128, BF_BN = 64, BF_KI = 32;
+
+__device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const WorkItem it, const float* __restrict__ spec,
+                                                    float* __restrict__ four) {
+  constexpr int BM = BF_BM, BN = BF_BN, KI = BF_KI;
+  constexpr int NCK = KI / KCH;              // k chunks per parity per step
+  constexpr int AU = 2 * 2 * NCK * BM / 256; // table units per thread
+  constexpr int FROW = BN + 4;               // epilogue exchange row (floats)
+  static_assert(AU == 8 && BN == 64 && BM * FROW * 4 <= 2 * 2 * NCK * (BM + BN) * 16, "tile shape");
+  __shared__ __align__(16) uint4 smem[2 * 2 * NCK * (BM + BN)];
+  uint4* As = smem;                          // [par][plane][chunk][BM]
+  uint4* Bs = smem + 2 * 2 * NCK * BM;       // [par][plane][chunk][BN]
+  float* Xs = (float*)smem;                  // epilogue: A parity [BM][FROW]
 
   const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
-  const u16* tab = (const u16*)p.tab;
-  const int twoF = 2 * p.F;
+  const int par = wave >> 1, rh = wave & 1;
   const int kpmax = mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1];
   const int nk = (kpmax + KI - 1) / KI;
 
-  int a_pl[AU], a_par[AU], a_ch[AU], a_row[AU], a_nch[AU];
-  int64_t a_base[AU];
-  bool a_ok[AU];
+  // Loads go through buffer descriptors, one per (parity, plane) table and
+  // one for the spectral array from index(m, m) on: reads past a table's
+  // padded k range return zero, so spectral values read past n = N (the
+  // next wavenumber's, or zeros past the end) meet zero table entries, and
+  // rows past the table or fields past F only feed outputs never stored.
+  // Table unit a = tid + 256 a holds row tid % 128 of chunk (2a + tid / 128) % 4,
+  // plane (a / 2) % 2, parity a / 4 (so its descriptor is uniform).
+  const u16* tab = (const u16*)p.tab;
+  const int a_row = tid & (BM - 1);
+  const __amdgpu_buffer_rsrc_t t00 = buffer_rsrc(tab + mi.toff[0], (uint32_t)mi.Kp[0] * mi.Lp * 2);
+  const __amdgpu_buffer_rsrc_t t01 = buffer_rsrc(tab + p.tab_plane + mi.toff[0], (uint32_t)mi.Kp[0] * mi.Lp * 2);
+  const __amdgpu_buffer_rsrc_t t10 = buffer_rsrc(tab + mi.toff[1], (uint32_t)mi.Kp[1] * mi.Lp * 2);
+  const __amdgpu_buffer_rsrc_t t11 = buffer_rsrc(tab + p.tab_plane + mi.toff[1], (uint32_t)mi.Kp[1] * mi.Lp * 2);
+  const uint32_t a_step = (uint32_t)NCK * mi.Lp * KCH * 2;  // bytes per step
+  uint32_t a_off[AU];
 #pragma unroll
-  for (int a = 0; a < AU; ++a) {
-    const int u = tid + 256 * a;
-    a_row[a] = u % BM;
-    a_ch[a] = (u / BM) % NC;
-    a_par[a] = (u / (BM * NC)) % 2;
-    a_pl[a] = u / (BM * NC * 2);
-    a_nch[a] = (a_par[a] ? mi.Kp[1] : mi.Kp[0]) / KCH;
-    a_ok[a] = it.t0 + a_row[a] < mi.Lp;
-    a_base[a] = (a_pl[a] ? plane : 0) + (a_par[a] ? mi.toff[1] : mi.toff[0]) + (int64_t)a_ch[a] * mi.Lp * KCH +
-                (int64_t)(it.t0 + a_row[a]) * KCH;
-  }
-  const int64_t a_step = (int64_t)NC * mi.Lp * KCH;
-  // spectral: thread (field fi, quarter q) owns n - m in [2 KI kc + 16 q, + 16)
-  const int fi = tid >> 2;
-  const int q = tid & 3;
+  for (int a = 0; a < AU; ++a)
+    a_off[a] = ((uint32_t)((2 * a + (tid >> 7)) & 3) * mi.Lp + (uint32_t)(it.t0 + a_row)) * KCH * 2;
+  // spectral values: lane fi = tid & 31 is the field, sg = tid >> 5 the
+  // segment of 8 consecutive n - m (both parities) within the step
+  const int fi = tid & 31, sg = tid >> 5;
   const int f = it.c0 / 2 + fi;
-  const bool f_ok = f < p.F;
-  const float2* sp = (const float2*)spec + ((int64_t)(f_ok ? f : 0) * p.nspec + mi.spec_off);
+  const uint32_t fc = (uint32_t)(f < p.F ? f : p.F - 1);
+  const __amdgpu_buffer_rsrc_t sr =
+      buffer_rsrc((const float2*)spec + mi.spec_off, (uint32_t)(((uint64_t)p.F * p.nspec - mi.spec_off) * 8));
+  const uint32_t b_off = (fc * (uint32_t)p.nspec + 8u * sg) * 8u;
+  const bool m0 = m == 0;
 
   uint4 ra[AU];
-  float2 rb[16];
+  float2 rb[8];
   auto fetch = [&](int kc) {
+    const uint32_t sa = (uint32_t)kc * a_step;
 #pragma unroll
     for (int a = 0; a < AU; ++a) {
-      const bool ok = a_ok[a] && (kc * NC + a_ch[a] < a_nch[a]);
-      ra[a] = ok ? gload((const uint4*)(tab + a_base[a] + kc * a_step)) : make_uint4(0, 0, 0, 0);
+      const int pa = a >> 2, pl = (a >> 1) & 1;
+      const __amdgpu_buffer_rsrc_t r = pa ? (pl ? t11 : t10) : (pl ? t01 : t00);
+      ra[a] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, a_off[a], sa, 0));
     }
+    const uint32_t sb = (uint32_t)kc * (2 * KI * 8);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int d = 2 * KI * kc + 16 * q + i;
-      float2 x = make_float2(0.f, 0.f);
-      if (f_ok && m + d <= p.N) x = gload(sp + d);
-      if (m == 0) x.y = 0.f;
-      rb[i] = x;
+    for (int q = 0; q < 4; ++q) {
+      const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off + 16 * q, sb, 0));
+      rb[2 * q] = make_float2(v.x, m0 ? 0.f : v.y);
+      rb[2 * q + 1] = make_float2(v.z, m0 ? 0.f : v.w);
     }
   };
 
-  f32x4 acc[2][IM][IN];
+  f32x4 acc[4][4];
 #pragma unroll
-  for (int par = 0; par < 2; ++par)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int i = 0; i < IM; ++i)
-#pragma unroll
-      for (int j = 0; j < IN; ++j) acc[par][i][j] = f32x4{0, 0, 0, 0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
   fetch(0);
   for (int kc = 0; kc < nk; ++kc) {
 #pragma unroll
-    for (int a = 0; a < AU; ++a) *(uint4*)&As[a_pl[a]][a_par[a]][a_row[a]][a_ch[a] * KCH] = ra[a];
-    // split the 16 complex values: parity i & 1, k = 8 q + i / 2
+    for (int a = 0; a < AU; ++a) {
+      const int pa = a >> 2, pl = (a >> 1) & 1, ch = (2 * a + (tid >> 7)) & 3;
+      As[((pa * 2 + pl) * NCK + ch) * BM + a_row] = ra[a];
+    }
+    // element i of the segment: parity i & 1, k = 4 sg + i / 2 within the step
+    // (chunk sg / 2, offset 4 (sg & 1)); columns 2 fi (re) and 2 fi + 1 (im)
 #pragma unroll
-    for (int par = 0; par < 2; ++par) {
+    for (int pa = 0; pa < 2; ++pa) {
 #pragma unroll
       for (int comp = 0; comp < 2; ++comp) {
-        uint32_t h[4], l[4];
+        uint32_t h[2], l[2];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float2 u = rb[4 * e + par], w = rb[4 * e + 2 + par];
+        for (int e = 0; e < 2; ++e) {
+          const float2 u = rb[4 * e + pa], w = rb[4 * e + 2 + pa];
           split2_bf16(comp ? u.y : u.x, comp ? w.y : w.x, &h[e], &l[e]);
         }
-        *(uint4*)&Bs[0][par][2 * fi + comp][8 * q] = make_uint4(h[0], h[1], h[2], h[3]);
-        *(uint4*)&Bs[1][par][2 * fi + comp][8 * q] = make_uint4(l[0], l[1], l[2], l[3]);
+        const int slot = ((pa * 2) * NCK + (sg >> 1)) * BN + 2 * fi + comp;
+        uint2* dh = (uint2*)(Bs + slot) + (sg & 1);
+        uint2* dl = (uint2*)(Bs + slot + NCK * BN) + (sg & 1);
+        *dh = make_uint2(h[0], h[1]);
+        *dl = make_uint2(l[0], l[1]);
       }
     }
     __syncthreads();
     if (kc + 1 < nk) fetch(kc + 1);
+    uint4 bh[4], bl[4];
 #pragma unroll
-    for (int par = 0; par < 2; ++par) {
-      uint4 ah[IM], al[IM], bh[IN], bl[IN];
-      const int kq = 8 * (lane >> 4);
+    for (int j = 0; j < 4; ++j) {
+      const int c = 16 * j + (lane & 15);
+      bh[j] = Bs[((par * 2 + 0) * NCK + (lane >> 4)) * BN + c];
+      bl[j] = Bs[((par * 2 + 1) * NCK + (lane >> 4)) * BN + c];
+    }
 #pragma unroll
-      for (int i = 0; i < IM; ++i) {
-        const int r = wr * WM + i * 16 + (lane & 15);
-        ah[i] = *(const uint4*)&As[0][par][r][kq];
-        al[i] = *(const uint4*)&As[1][par][r][kq];
+    for (int i = 0; i < 4; ++i) {
+      const int r = 64 * rh + 16 * i + (lane & 15);
+      const uint4 ah = As[((par * 2 + 0) * NCK + (lane >> 4)) * BM + r];
+      const uint4 al = As[((par * 2 + 1) * NCK + (lane >> 4)) * BM + r];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = mfma_bf16(al, bh[j], acc[i][j]);
+        acc[i][j] = mfma_bf16(ah, bl[j], acc[i][j]);
+        acc[i][j] = mfma_bf16(ah, bh[j], acc[i][j]);
       }
-#pragma unroll
-      for (int j = 0; j < IN; ++j) {
-        const int c = wc * WN + j * 16 + (lane & 15);
-        bh[j] = *(const uint4*)&Bs[0][par][c][kq];
-        bl[j] = *(const uint4*)&Bs[1][par][c][kq];
-      }
-#pragma unroll
-      for (int i = 0; i < IM; ++i)
-#pragma unroll
-        for (int j = 0; j < IN; ++j) {
-          acc[par][i][j] = mfma_bf16(al[i], bh[j], acc[par][i][j]);
-          acc[par][i][j] = mfma_bf16(ah[i], bl[j], acc[par][i][j]);
-          acc[par][i][j] = mfma_bf16(ah[i], bh[j], acc[par][i][j]);
-        }
     }
     __syncthreads();
   }
 
-  const int64_t rowlen = 2 * (int64_t)p.Fp;
+  // epilogue: the parity-1 waves hand A to the parity-0 waves through LDS;
+  // element (i, j, e): row 64 rh + 16 i + 4 (lane / 16) + e, column 16 j + lane % 16
+  if (par == 1) {
 #pragma unroll
-  for (int i = 0; i < IM; ++i) {
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int row = it.t0 + wr * WM + i * 16 + 4 * (lane >> 4) + e;
-      if (row >= mi.L) continue;
-      const RingInfo rn = gload(p.rings + mi.first_ring + row);
-      float* dn = four + (rn.frow + m) * rowlen;
-      float* ds = four + (gload(p.rings + rn.mirror).frow + m) * rowlen;
+      for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int j = 0; j < IN; ++j) {
-        const int col = it.c0 + wc * WN + j * 16 + (lane & 15);
-        if (col < twoF) {
-          const float S = acc[0][i][j][e];
-          const float A = acc[1][i][j][e];
-          gstore(dn + col, S + A);
-          gstore(ds + col, S - A);
+        for (int j = 0; j < 4; ++j)
+          Xs[(64 * rh + 16 * i + 4 * (lane >> 4) + e) * FROW + 16 * j + (lane & 15)] = acc[i][j][e];
+  }
+  __syncthreads();
+  if (par == 0) {
+    const int64_t rowlen = 2 * (int64_t)p.Fp;
+    const int twoF = 2 * p.F;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rl = 64 * rh + 16 * i + 4 * (lane >> 4) + e;
+        const int row = it.t0 + rl;
+        if (row >= mi.L) continue;
+        const RingInfo rn = gload(p.rings + mi.first_ring + row);
+        float* dn = four + (rn.frow + m) * rowlen;
+        float* ds = four + (gload(p.rings + rn.mirror).frow + m) * rowlen;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int cl = 16 * j + (lane & 15);
+          const int col = it.c0 + cl;
+          if (col < twoF) {
+            const float S = acc[i][j][e];
+            const float A = Xs[rl * FROW + cl];
+            gstore(dn + col, S + A);
+            gstore(ds + col, S - A);
+          }
         }
       }
     }
   }
+  __syncthreads();
 }
 
 // Analysis in BF16 split precision: out^T[c][k] = sum_j X^T[c][j] T[j][k]
@@ -751,7 +791,6 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(const DevPlan* 
   }
 }
 
-template <int BM, int BN>
 __global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(const DevPlan* __restrict__ plans,
                                                                       const WorkItem* __restrict__ items, int nitems,
                                                                       const IoBind* __restrict__ io, IoBind io0) {
@@ -760,12 +799,12 @@ __global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(const DevP
     if (it.m < 0) continue;  // empty slot of the work list
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    inverse_bf16x3_tile<BM, BN>(p, it, (const float*)b.spec, (float*)b.ws);
+    inverse_bf16x3_tile(p, it, (const float*)b.spec, (float*)b.ws);
   }
 }
 
 template <int BC, int BK>
-__global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(const DevPlan* __restrict__ plans,
+__global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const DevPlan* __restrict__ plans,
                                                                      const WorkItem* __restrict__ items, int nitems,
                                                                      const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
@@ -787,18 +826,18 @@ __global__ __launch_bounds__(256) void legendre_direct_bf16x3_kernel(const DevPl
 #define INV_F32_C128 legendre_inverse_kernel<float, 128, 128, 16, 2>
 #define INV_F32_C64 legendre_inverse_kernel<float, 128, 64, 16, 2>
 #define INV_F32_C32 legendre_inverse_kernel<float, 128, 32, 16, 1>
-#define INV_BF16_C128 legendre_inverse_bf16x3_kernel<128, 128>
+#define INV_BF16 legendre_inverse_bf16x3_kernel
 #define DIR_F64_C64 legendre_direct_kernel<double, 64, 64, 16, 2>
 #define DIR_F64_C32 legendre_direct_kernel<double, 32, 64, 16, 4>
 #define DIR_F32_C128 legendre_direct_kernel<float, 128, 64, 16, 2>
 #define DIR_F32_C64 legendre_direct_kernel<float, 64, 64, 16, 2>
 #define DIR_F32_C32 legendre_direct_kernel<float, 32, 64, 16, 4>
-#define DIR_BF16_C128 legendre_direct_bf16x3_kernel<128, 64>
+#define DIR_BF16 legendre_direct_bf16x3_kernel<128, 64>
 
 bool legendre_variant_supported(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C64 || variant == TILE_C32;
   if (prec == SHT_FP32) return variant >= 0 && variant < NUM_TILE_VARIANTS;
-  return variant == TILE_C128;
+  return variant == TILE_C64;  // bf16x3: synthesis 128 x 64, analysis 64 k x 128 columns
 }
 
 void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols) {
@@ -806,7 +845,7 @@ void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* di
   *inv_rows = (prec == SHT_FP64) ? 64 : 128;
   *inv_cols = cols;
   *dir_rows = 64;
-  *dir_cols = cols;
+  *dir_cols = (prec == SHT_BF16X3) ? 128 : cols;
 }
 
 template <typename K>
@@ -818,14 +857,14 @@ static const void* inverse_fn(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C32 ? fn(INV_F64_C32) : fn(INV_F64_C64);
   if (prec == SHT_FP32)
     return variant == TILE_C128 ? fn(INV_F32_C128) : variant == TILE_C64 ? fn(INV_F32_C64) : fn(INV_F32_C32);
-  return fn(INV_BF16_C128);
+  return fn(INV_BF16);
 }
 
 static const void* direct_fn(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C32 ? fn(DIR_F64_C32) : fn(DIR_F64_C64);
   if (prec == SHT_FP32)
     return variant == TILE_C128 ? fn(DIR_F32_C128) : variant == TILE_C64 ? fn(DIR_F32_C64) : fn(DIR_F32_C32);
-  return fn(DIR_BF16_C128);
+  return fn(DIR_BF16);
 }
 
 int legendre_blocks_per_cu(int prec, int variant, bool inverse) {
