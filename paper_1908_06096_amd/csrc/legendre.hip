@@ -605,7 +605,9 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
 // Analysis in BF16 split precision: out^T[c][k] = sum_j X^T[c][j] T[j][k]
 // with K = rings.  Both operands need the rings contiguous per lane, so the
 // Fourier rows are gathered 8 rings at a time per column and the table
-// chunks ([ring][8 k]) are transposed 8 x 8 in registers.
+// chunks ([ring][8 k]) are transposed 8 x 8 in registers.  The K loop runs
+// without guards (see the unit comments below); ring row offsets are
+// looked up a step ahead of the rows' loads.
 template <int BC, int BK>
 __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkItem it,
                                                    const float* __restrict__ four, float* __restrict__ spec) {
@@ -631,39 +633,45 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   const int64_t rowlen = 2 * (int64_t)p.Fp;
   const int nj = (mi.L + KJ - 1) / KJ;
 
-  // X unit: (parity, column quad, ring octet)
+  // X unit: (parity, column quad, ring octet).  Rings past L are read at
+  // ring L - 1 (their table rows are zero or past the table), and columns
+  // past the row end (outputs never stored) are clamped into the row.
   const int x_oct = tid % (KJ / 8);
   const int x_cq = (tid / (KJ / 8)) % (BC / 4);
   const int x_par = tid / ((KJ / 8) * (BC / 4));
-  const int x_c = it.c0 + 4 * x_cq;
-  // table unit: (plane, parity, chunk, ring octet)
+  const int x_c = min(it.c0 + 4 * x_cq, 2 * p.Fp - 4);
+  // table unit: (plane, parity, chunk, ring octet), read through one buffer
+  // descriptor per (parity, plane): chunks past the table return zero
   const int t_oct = tid % (KJ / 8);
   const int t_ch = (tid / (KJ / 8)) % NCH;
   const int t_par = (tid / ((KJ / 8) * NCH)) % 2;
   const int t_pl = tid / ((KJ / 8) * NCH * 2);
-  const int t_kch = it.t0 / KCH + t_ch;
-  const bool t_ok = tid < TUNITS && t_kch * KCH < (t_par ? mi.Kp[1] : mi.Kp[0]);
-  const int64_t t_base = (t_pl ? plane : 0) + (t_par ? mi.toff[1] : mi.toff[0]) + (int64_t)t_kch * mi.Lp * KCH;
+  const bool t_on = tid < TUNITS;  // whole waves
+  const __amdgpu_buffer_rsrc_t trs =
+      buffer_rsrc(tab + (t_pl ? plane : 0) + (t_par ? mi.toff[1] : mi.toff[0]),
+                  (uint32_t)(t_par ? mi.Kp[1] : mi.Kp[0]) * mi.Lp * 2);
+  const uint32_t t_off = ((uint32_t)(it.t0 / KCH + t_ch) * mi.Lp + 8u * t_oct) * (KCH * 2);
 
+  // the Fourier rows of the rings of step jc + 1 are looked up one step ahead
+  int64_t fr[8], fr_next[8];
+  auto fetch_rows = [&](int jc, int64_t* dst) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int r = min(jc * KJ + 8 * x_oct + e, mi.L - 1);
+      dst[e] = gload(&p.rings[mi.first_ring + r].frow);
+    }
+  };
   float4 rx[8];
   uint4 rt[8];
   auto fetch = [&](int jc) {
-    const int r0 = jc * KJ + 8 * x_oct;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = r0 + e;
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < mi.L && x_c < 2 * p.Fp) {
-        const int64_t fr = gload(p.rings + mi.first_ring + r).frow;
-        v = gload((const float4*)(four + ((fr + m) * 2 + x_par) * rowlen + x_c));
-      }
-      rx[e] = v;
-    }
-    const int t0 = jc * KJ + 8 * t_oct;
+    for (int e = 0; e < 8; ++e)
+      rx[e] = gload((const float4*)(four + ((fr[e] + m) * 2 + x_par) * rowlen + x_c));
+    if (t_on) {
+      const uint32_t so = (uint32_t)jc * KJ * (KCH * 2);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = t0 + e;
-      rt[e] = (t_ok && r < mi.Lp) ? gload((const uint4*)(tab + t_base + (int64_t)r * KCH)) : make_uint4(0, 0, 0, 0);
+      for (int e = 0; e < 8; ++e)
+        rt[e] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(trs, t_off + e * (KCH * 2), so, 0));
     }
   };
 
@@ -675,7 +683,9 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
 #pragma unroll
       for (int j = 0; j < IK; ++j) acc[par][i][j] = f32x4{0, 0, 0, 0};
 
+  fetch_rows(0, fr);
   fetch(0);
+  if (nj > 1) fetch_rows(1, fr_next);
   for (int jc = 0; jc < nj; ++jc) {
     // X: 4 columns x 8 rings -> per column 8 rings of hi and lo
 #pragma unroll
@@ -703,11 +713,16 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
           const uint32_t b = w[4 * (2 * d + 1) + (kk >> 1)];
           o[d] = (kk & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
         }
-        if (tid < TUNITS) *(uint4*)&Ts[t_pl][t_par][t_ch * KCH + kk][8 * t_oct] = make_uint4(o[0], o[1], o[2], o[3]);
+        if (t_on) *(uint4*)&Ts[t_pl][t_par][t_ch * KCH + kk][8 * t_oct] = make_uint4(o[0], o[1], o[2], o[3]);
       }
     }
     __syncthreads();
-    if (jc + 1 < nj) fetch(jc + 1);
+    if (jc + 1 < nj) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) fr[e] = fr_next[e];
+      fetch(jc + 1);
+      if (jc + 2 < nj) fetch_rows(jc + 2, fr_next);
+    }
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
       uint4 ah[IC], al[IC], bh[IK], bl[IK];

@@ -17,9 +17,11 @@ namespace shtmi {
 // ---------------------------------------------------------------------------
 
 // Legendre tables are stored per (m, parity) as chunks of KCH consecutive
-// k (n = m + parity + 2k); each chunk is [rows][KCH], rows padded to ROWPAD.
+// k (n = m + parity + 2k); each chunk is [rows][KCH], rows padded with zeros
+// to ROWPAD, a multiple of every product's ring step (the BF16 analysis
+// reads rings 32 at a time, unguarded).
 constexpr int KCH = 8;
-constexpr int ROWPAD = 16;
+constexpr int ROWPAD = 32;
 // Field stride of the Fourier workspace (complex elements) is F rounded up.
 constexpr int FPAD = 16;
 
