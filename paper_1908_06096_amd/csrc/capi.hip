@@ -121,14 +121,16 @@ int cu_count() {
   return n;
 }
 
-// Default column-tile variant for 2F real columns: the narrowest tile that
-// covers them (wider tiles only waste MFMA work on padding columns).
+// Default column-tile variant for 2F real columns: 32 columns when they
+// cover them, else 64.  The 128-column FP32 tiles hold twice the
+// accumulators (two work groups per CU instead of three) and pad 2F further;
+// at TCo1279 x 411 they measured 8% (synthesis) and 22% (analysis) slower.
+// sht_plan_set_tile and the batch autotuner can still choose them.
 int default_variant(int prec, int F) {
   const int cols = 2 * F;
   if (prec == SHT_BF16X3) return TILE_C64;
   if (cols <= 32) return TILE_C32;
-  if (cols <= 64 || prec == SHT_FP64) return TILE_C64;
-  return TILE_C128;
+  return TILE_C64;
 }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
