@@ -1,0 +1,97 @@
+"""Parity at the full configured sizes (TCo1279 O1280 x 411 fields in FP32
+and bf16x3, T399 full 400 x 800 x 411 in FP64), with the plans and launches
+the benchmark times, on outputs the oracle computes one by one: sampled
+rings of the synthesis, sampled wavenumbers of the analysis, for fields at
+the start, middle and ragged end of the field range.  The inputs are 4
+distinct seeded fields repeated to 411 on the device (field f is field
+f mod 4), so the oracle only ever works on 4 fields."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import TOL, np_dtype, rel_l2
+from paper_1908_06096_amd.inputs import grid_noise, spectral_coefficients
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    (1279, "octahedral", 411, "fp32"),
+    (1279, "octahedral", 411, "bf16x3"),
+    (399, "full", 411, "fp64"),
+]
+FIELDS = [0, 205, 410]
+D = 4
+
+
+@pytest.fixture(scope="module")
+def sht():
+    from paper_1908_06096_amd import sht as mod
+
+    return mod
+
+
+def _ids(c):
+    return "T%d-%s-F%d-%s" % c
+
+
+def _spec(plan, seed):
+    s = spectral_coefficients(plan.truncation, D, seed=seed, dtype=np_dtype(plan.precision))
+    idx = torch.arange(plan.nfields, device="cuda") % D
+    t = torch.from_numpy(np.ascontiguousarray(s)).cuda()[idx].contiguous()
+    return t, s[..., 0].astype(np.float64) + 1j * s[..., 1].astype(np.float64)
+
+
+def _grid(plan, seed):
+    g = grid_noise(plan.npts, D, seed=seed, dtype=np_dtype(plan.precision))
+    idx = torch.arange(plan.nfields, device="cuda") % D
+    t = torch.from_numpy(np.ascontiguousarray(g)).cuda()[idx].contiguous()
+    return t, g.astype(np.float64)
+
+
+def _rings(nlat):
+    nh = nlat // 2
+    return sorted({0, 1, nlat // 5, nh - 1, nh, nlat - 2, nlat - 1})
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_full_size_sampled(sht, case):
+    N, grid, F, prec = case
+    geo = oracle.grid_geometry(N, grid)
+    with sht.Plan(N, grid, F, prec) as plan:
+        # synthesis on sampled rings
+        spec_t, spec_c = _spec(plan, seed=21)
+        g = plan.inverse(spec_t)
+        rings = _rings(geo["nlat"])
+        _four, ref = oracle.inverse(spec_c, N, grid, rings=rings)
+        got, want = [], []
+        for fo in FIELDS:
+            for j in rings:
+                got.append(g[fo, geo["off"][j]:geo["off"][j + 1]].double().cpu().numpy())
+                want.append(ref[j][fo % D])
+        err = rel_l2(np.concatenate(got), np.concatenate(want))
+        print(f"[{_ids(case)}] synthesis on rings {rings}: rel L2 {err:.3e}", flush=True)
+        assert err <= TOL[prec]
+
+        # round trip of the same fields (band-limited input: exact up to rounding)
+        back = plan.direct(g)
+        torch.cuda.synchronize()
+        b = back[FIELDS].double().cpu().numpy()
+        err = rel_l2(b[..., 0] + 1j * b[..., 1], spec_c[[fo % D for fo in FIELDS]])
+        print(f"[{_ids(case)}] round trip: rel L2 {err:.3e}", flush=True)
+        assert err <= TOL[prec]
+        del g, back, spec_t
+
+        # analysis of white noise on sampled wavenumbers
+        grid_t, grid_np = _grid(plan, seed=22)
+        s = plan.direct(grid_t)
+        ms = sorted({0, 1, 2, N // 2, N - 1, N})
+        _f, ref = oracle.direct(grid_np, N, grid, ms=ms)
+        sel = np.concatenate([np.arange(oracle.spec_index(N, m, m), oracle.spec_index(N, m, N) + 1) for m in ms])
+        sh = s[FIELDS][:, torch.from_numpy(sel).cuda()].double().cpu().numpy()
+        got = sh[..., 0] + 1j * sh[..., 1]
+        want = ref[[fo % D for fo in FIELDS]][:, sel]
+        err = rel_l2(got, want)
+        print(f"[{_ids(case)}] analysis on m {ms}: rel L2 {err:.3e}", flush=True)
+        assert err <= TOL[prec]
