@@ -277,7 +277,7 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
     kk[i] = Ns > 1 ? b - (int)__umulhi((uint32_t)b, magic) * Ns : 0;
     if (b < nb) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = buf[lds_ix(b + r * nb)];
+      for (int r = 0; r < R; ++r) v[i][r] = lload(buf + lds_ix(b + r * nb));
       if (Ns > 1) {
         const C* t = tw + kk[i] * (R - 1) - 1;
 #pragma unroll
@@ -297,11 +297,11 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
       for (int r = 0; r < R; ++r) {
         const int o = d + r * Ns;
         if constexpr (MODE == OUT_PLAIN) {
-          buf[lds_ix(o)] = v[i][r];
+          lstore(buf + lds_ix(o), v[i][r]);
         } else if constexpr (MODE == OUT_KHAT) {
-          buf[lds_ix(o)] = cconj(cmul(v[i][r], gload(aux + o)));
+          lstore(buf + lds_ix(o), cconj(cmul(v[i][r], gload(aux + o))));
         } else if constexpr (MODE == OUT_CHIRP) {
-          if (o < h) buf[lds_ix(o)] = cmul(gload(aux + o), cconj(v[i][r]));
+          if (o < h) lstore(buf + lds_ix(o), cmul(gload(aux + o), cconj(v[i][r])));
         } else if constexpr (MODE == OUT_GRID) {
           if (io && o < h) gstore(io + o, cconj(v[i][r]));
         } else {

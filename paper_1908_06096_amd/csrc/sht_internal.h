@@ -66,6 +66,29 @@ __device__ __forceinline__ T gload(const T* p) {
     return *(const SHT_GLOBAL T*)p;
   }
 }
+// The same for LDS (address space 3), for pointers the compiler cannot
+// trace to a __shared__ object (arguments of non-inlined functions), which
+// would otherwise become FLAT accesses.
+#define SHT_LDS __attribute__((address_space(3)))
+template <typename T>
+__device__ __forceinline__ T lload(const T* p) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
+  if constexpr (sizeof(T) == 8) {
+    return __builtin_bit_cast(T, *(const SHT_LDS gword2*)p);
+  } else {
+    return __builtin_bit_cast(T, *(const SHT_LDS gword4*)p);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void lstore(T* p, const T& v) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
+  if constexpr (sizeof(T) == 8) {
+    *(SHT_LDS gword2*)p = __builtin_bit_cast(gword2, v);
+  } else {
+    *(SHT_LDS gword4*)p = __builtin_bit_cast(gword4, v);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void gstore(T* p, const T& v) {
   if constexpr (sizeof(T) == 8 && alignof(T) >= 8) {
