@@ -54,7 +54,7 @@ __device__ inline C cscale(C a, T s) {
 // elements (R Ns with Ns < 64), which unpadded would put most lanes of a
 // wave on the same banks; the spare slots spread them.  A transform of L
 // elements spans lds_span(L) slots.
-constexpr int FFT_PAD_SHIFT = 4;
+constexpr int FFT_PAD_SHIFT = 5;
 __host__ __device__ constexpr int lds_ix(int i) { return i + (i >> FFT_PAD_SHIFT); }
 __host__ __device__ constexpr int lds_span(int L) { return lds_ix(L - 1) + 1; }
 
@@ -407,37 +407,62 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
   const int gs = cl.gshift, G = 1 << gs;
   const int nt = FFT_THREADS >> gs;
   const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
-  const int Q = blue ? L : h;
   const int S = lds_span(L);
   {
-    const int n = Q << gs;
-    for (int e0 = threadIdx.x; e0 < n; e0 += FFT_SWEEP * FFT_THREADS) {
-      C xq[FFT_SWEEP], xr[FFT_SWEEP], pq[FFT_SWEEP], cq[FFT_SWEEP];
+    // Z_q and Z_{h-q} are built from the same two coefficients X_q and
+    // X_{h-q}, so pair p = q (0 <= q <= h/2) loads them once and writes both
+    const int np = (h / 2 + 1) << gs;
+    for (int e0 = threadIdx.x; e0 < np; e0 += FFT_SWEEP * FFT_THREADS) {
+      C xa[FFT_SWEEP], xb[FFT_SWEEP], pa[FFT_SWEEP], pb[FFT_SWEEP], ca[FFT_SWEEP], cb[FFT_SWEEP];
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int e = e0 + u * FFT_THREADS;
         const int s = e & (G - 1), q = e >> gs, q2 = h - q;
-        const bool ok = e < n && q < h && fb + s < fend;
+        const bool ok = e < np && fb + s < fend;
+        const bool two = ok && q >= 1 && q2 != q;  // q2 < h is a distinct index
         const C* cf = fc + ri.frow * Fp + fb + s;
-        xq[u] = (ok && q <= mmax) ? gload(cf + q * Fp) : C{0, 0};
-        xr[u] = (ok && q >= 1 && q2 <= mmax) ? gload(cf + q2 * Fp) : C{0, 0};
-        pq[u] = ok ? gload(post + q) : C{1, 0};
-        cq[u] = (ok && blue) ? gload(chirp + q) : C{1, 0};
+        xa[u] = (ok && q <= mmax) ? gload(cf + q * Fp) : C{0, 0};
+        xb[u] = (ok && q >= 1 && q2 <= mmax) ? gload(cf + q2 * Fp) : C{0, 0};
+        pa[u] = ok ? gload(post + q) : C{1, 0};
+        pb[u] = two ? gload(post + q2) : C{1, 0};
+        ca[u] = (ok && blue) ? gload(chirp + q) : C{1, 0};
+        cb[u] = (two && blue) ? gload(chirp + q2) : C{1, 0};
       }
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int e = e0 + u * FFT_THREADS;
-        if (e < n) {
-          const int s = e & (G - 1), q = e >> gs;
-          C x = xq[u];
-          if (q == 0) x.y = 0;
-          const C xr_ = cconj(xr[u]);
-          const C sm = cadd(x, xr_);
-          const C t = cmul(cconj(pq[u]), csub(x, xr_));
-          C y = C{sm.x - t.y, -(sm.y + t.x)};  // conj(sm + i t); zero where nothing was loaded
-          if (blue) y = cmul(y, cq[u]);
-          buf[s * S + lds_ix(q)] = y;
+        if (e < np) {
+          const int s = e & (G - 1), q = e >> gs, q2 = h - q;
+          C A = xa[u];
+          if (q == 0) A.y = 0;  // Im c_0 is dropped
+          const C B = xb[u];
+          {
+            // Z_q from X_q = A and conj X_{h-q} = conj B; zero where nothing was loaded
+            const C xr = cconj(B);
+            const C sm = cadd(A, xr);
+            const C t = cmul(cconj(pa[u]), csub(A, xr));
+            C y = C{sm.x - t.y, -(sm.y + t.x)};  // conj(sm + i t)
+            if (blue) y = cmul(y, ca[u]);
+            buf[s * S + lds_ix(q)] = y;
+          }
+          if (q >= 1 && q2 != q) {
+            // Z_{h-q} from X_{h-q} = B and conj X_q = conj A
+            const C xr = cconj(A);
+            const C sm = cadd(B, xr);
+            const C t = cmul(cconj(pb[u]), csub(B, xr));
+            C y = C{sm.x - t.y, -(sm.y + t.x)};
+            if (blue) y = cmul(y, cb[u]);
+            buf[s * S + lds_ix(q2)] = y;
+          }
         }
+      }
+    }
+    // chirp-z classes: zero padding h <= t < L
+    if (blue) {
+      const int nz = (L - h) << gs;
+      for (int e = threadIdx.x; e < nz; e += FFT_THREADS) {
+        const int s = e & (G - 1), t = h + (e >> gs);
+        buf[s * S + lds_ix(t)] = C{0, 0};
       }
     }
     __syncthreads();
