@@ -58,6 +58,34 @@ constexpr int FFT_PAD_SHIFT = 5;
 __host__ __device__ constexpr int lds_ix(int i) { return i + (i >> FFT_PAD_SHIFT); }
 __host__ __device__ constexpr int lds_span(int L) { return lds_ix(L - 1) + 1; }
 
+// 8- and 16-byte values in LDS through an address-space-3 pointer (32-bit
+// addresses), and from a table through a raw buffer descriptor whose range
+// is not checked (every offset used is inside the table).
+template <typename C>
+__device__ __forceinline__ C lds_load(const SHT_LDS C* p) {
+  if constexpr (sizeof(C) == 8) return __builtin_bit_cast(C, *(const SHT_LDS gword2*)p);
+  else return __builtin_bit_cast(C, *(const SHT_LDS gword4*)p);
+}
+template <typename C>
+__device__ __forceinline__ void lds_store(SHT_LDS C* p, const C& v) {
+  if constexpr (sizeof(C) == 8) *(SHT_LDS gword2*)p = __builtin_bit_cast(gword2, v);
+  else *(SHT_LDS gword4*)p = __builtin_bit_cast(gword4, v);
+}
+// The base is the same on every lane (a table of the transform's class);
+// reading it from the first lane tells the compiler so, which keeps the
+// descriptor in scalar registers.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base) {
+  const uint64_t a = (uint64_t)base;
+  const uint64_t u = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)u, (short)0, (int)0x7fffffff, 0x00020000);
+}
+template <typename C>
+__device__ __forceinline__ C buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  if constexpr (sizeof(C) == 8) return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+  else return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0));
+}
+
 // exp(-2 pi i j / R) at compile time: the angle is reduced exactly to
 // |r| <= pi/4 from the nearest quarter turn (4j - qR is an integer), then
 // sine and cosine of r are summed as Taylor series to double precision.
@@ -260,7 +288,7 @@ enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2, OUT_GRID = 3, OUT_GRI
 // are allocated for it alone.  Every thread of the work group calls it (the
 // barriers).
 template <typename T, int R, int MODE>
-__device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, int Ns,
+__device__ __noinline__ void stockham_pass(SHT_LDS typename V2T<T>::type* buf, int L, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                            typename V2T<T>::type* io, int h, int lt, int nt) {
   typedef typename V2T<T>::type C;
@@ -269,6 +297,10 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
   // b mod Ns by multiply-high: for b < 2^14 and 1 < Ns <= 2^13,
   // floor(b / Ns) = umulhi(b, ceil(2^32 / Ns)) exactly
   const uint32_t magic = Ns > 1 ? 0xFFFFFFFFu / (uint32_t)Ns + 1u : 0u;
+  // twiddles and the chirp-z factors through buffer descriptors: 32-bit
+  // offsets, the per-r displacement in the instruction's immediate
+  const __amdgpu_buffer_rsrc_t trs = buffer_rsrc(tw);
+  const __amdgpu_buffer_rsrc_t ars = buffer_rsrc(aux);
   C v[MAXB][R];
   int kk[MAXB];
 #pragma unroll
@@ -277,11 +309,11 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
     kk[i] = Ns > 1 ? b - (int)__umulhi((uint32_t)b, magic) * Ns : 0;
     if (b < nb) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = lload(buf + lds_ix(b + r * nb));
+      for (int r = 0; r < R; ++r) v[i][r] = lds_load(buf + lds_ix(b + r * nb));
       if (Ns > 1) {
-        const C* t = tw + kk[i] * (R - 1) - 1;
+        const uint32_t t = (uint32_t)(kk[i] * (R - 1)) * (uint32_t)sizeof(C);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], gload(t + r));
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], buffer_load<C>(trs, t + (r - 1) * sizeof(C)));
       }
     }
   }
@@ -296,16 +328,17 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int o = d + r * Ns;
+        const uint32_t ao = (uint32_t)o * (uint32_t)sizeof(C);
         if constexpr (MODE == OUT_PLAIN) {
-          lstore(buf + lds_ix(o), v[i][r]);
+          lds_store(buf + lds_ix(o), v[i][r]);
         } else if constexpr (MODE == OUT_KHAT) {
-          lstore(buf + lds_ix(o), cconj(cmul(v[i][r], gload(aux + o))));
+          lds_store(buf + lds_ix(o), cconj(cmul(v[i][r], buffer_load<C>(ars, ao))));
         } else if constexpr (MODE == OUT_CHIRP) {
-          if (o < h) lstore(buf + lds_ix(o), cmul(gload(aux + o), cconj(v[i][r])));
+          if (o < h) lds_store(buf + lds_ix(o), cmul(buffer_load<C>(ars, ao), cconj(v[i][r])));
         } else if constexpr (MODE == OUT_GRID) {
           if (io && o < h) gstore(io + o, cconj(v[i][r]));
         } else {
-          if (io && o < h) gstore(io + o, cmul(cconj(gload(aux + o)), v[i][r]));
+          if (io && o < h) gstore(io + o, cmul(cconj(buffer_load<C>(ars, ao)), v[i][r]));
         }
       }
     }
@@ -314,7 +347,7 @@ __device__ __noinline__ void stockham_pass(typename V2T<T>::type* buf, int L, in
 }
 
 template <typename T, int MODE>
-__device__ __forceinline__ void pass_dispatch(int R, typename V2T<T>::type* buf, int L, int Ns,
+__device__ __forceinline__ void pass_dispatch(int R, SHT_LDS typename V2T<T>::type* buf, int L, int Ns,
                                      const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                      typename V2T<T>::type* io, int h, int lt, int nt) {
 #define SHT_PASS(RR) stockham_pass<T, RR, MODE>(buf, L, Ns, tw, aux, io, h, lt, nt)
@@ -339,7 +372,7 @@ __device__ __forceinline__ void pass_dispatch(int R, typename V2T<T>::type* buf,
 // Forward DFT of L points held in LDS (natural order in and out); the last
 // pass applies MODE with aux and io.
 template <typename T, int MODE>
-__device__ __forceinline__ void fft_lds(typename V2T<T>::type* buf, int L, int nrad, const int32_t* rad,
+__device__ __forceinline__ void fft_lds(SHT_LDS typename V2T<T>::type* buf, int L, int nrad, const int32_t* rad,
                                         const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                         typename V2T<T>::type* io, int h, int lt, int nt) {
   int Ns = 1;
@@ -359,7 +392,7 @@ __device__ __forceinline__ void fft_lds(typename V2T<T>::type* buf, int L, int n
 // when io is null).  Chirp-z: A = DFT_L(a), B = conj(A khat),
 // Z_q = c_q conj(DFT_L(B))_q.
 template <typename T, bool GRID_OUT>
-__device__ __forceinline__ void dft_h(typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
+__device__ __forceinline__ void dft_h(SHT_LDS typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
                       const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
   if (!c.bluestein) {
@@ -470,7 +503,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
     const int f = fb + sub;
     C* g = f < fend ? (C*)(grid + (int64_t)f * p.npts + ri.goff) : nullptr;
     // the last pass writes the grid (the conjugate of the inverse transform)
-    dft_h<T, true>(buf + sub * S, cl, rad, tabs, g, lt, nt);
+    dft_h<T, true>((SHT_LDS C*)(buf + sub * S), cl, rad, tabs, g, lt, nt);
   }
 }
 
@@ -529,7 +562,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
         }
       }
       __syncthreads();
-      dft_h<T, false>(dst, cl, rad, tabs, nullptr, lt, nt);
+      dft_h<T, false>((SHT_LDS C*)dst, cl, rad, tabs, nullptr, lt, nt);
       const int nm = M << gs;
       for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * FFT_THREADS) {
         C pm[FFT_SWEEP];
