@@ -22,6 +22,19 @@ namespace shtmi {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+// Raw buffer descriptor over `bytes` bytes from `base` (no stride; loads
+// past the range return zero), and 8- / 16-byte loads through one with a
+// lane offset and a uniform offset (bytes).
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename V>
+__device__ __forceinline__ V rsrc_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  static_assert(sizeof(V) == 8 || sizeof(V) == 16, "8- or 16-byte values");
+  if constexpr (sizeof(V) == 8) return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  else return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 template <typename T>
 struct Acc;
 template <>
@@ -110,46 +123,53 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
   const int kpmax = mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1];
   const int nk = (kpmax + KI - 1) / KI;
 
-  // table units owned by this thread
-  int64_t a_base[AU];
-  int a_par[AU], a_ch[AU], a_row[AU], a_nch[AU];
-  bool a_ok[AU];
+  // Table and spectral loads go through buffer descriptors: reads past a
+  // parity table's padded k range return zero, so spectral values read past
+  // n = N (another wavenumber's, finite) meet zero table entries; rows past
+  // the table and fields past F only feed outputs that are never stored.
+  // Unit a = tid + 256 a: parity and chunk are the same across a wave (its
+  // descriptor is uniform), the row is the lane's.
+  uint32_t a_off[AU];
+  int a_par[AU], a_ch[AU], a_row[AU];
 #pragma unroll
   for (int a = 0; a < AU; ++a) {
     const int u = tid + 256 * a;
-    a_par[a] = u / (NC * BM);
-    a_ch[a] = (u / BM) % NC;
+    a_par[a] = __builtin_amdgcn_readfirstlane(u / (NC * BM));
+    a_ch[a] = __builtin_amdgcn_readfirstlane((u / BM) % NC);
     a_row[a] = u % BM;
-    const int64_t toff = a_par[a] ? mi.toff[1] : mi.toff[0];
-    a_nch[a] = (a_par[a] ? mi.Kp[1] : mi.Kp[0]) / KCH;
-    a_ok[a] = it.t0 + a_row[a] < mi.Lp;
-    a_base[a] = toff + (int64_t)a_ch[a] * mi.Lp * KCH + (int64_t)(it.t0 + a_row[a]) * KCH;
+    a_off[a] = ((uint32_t)a_ch[a] * mi.Lp + (uint32_t)(it.t0 + a_row[a])) * (KCH * (uint32_t)sizeof(T));
   }
-  const int64_t a_step = (int64_t)NC * mi.Lp * KCH;
-  // spectral values owned by this thread: field fi, n offsets q + TPF j
+  const __amdgpu_buffer_rsrc_t t_rs0 = buffer_rsrc(tab + mi.toff[0], (uint32_t)mi.Kp[0] * mi.Lp * (uint32_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t t_rs1 = buffer_rsrc(tab + mi.toff[1], (uint32_t)mi.Kp[1] * mi.Lp * (uint32_t)sizeof(T));
+  const uint32_t a_step = (uint32_t)NC * mi.Lp * KCH * (uint32_t)sizeof(T);  // bytes per iteration
+  // spectral values owned by this thread: field fi, n offsets q + TPF j;
+  // the descriptor starts at the tile's first field
   const int fi = tid / TPF;
   const int q = tid % TPF;
-  const int f = it.c0 / 2 + fi;
-  const bool f_ok = f < p.F;
-  const C2* sp = (const C2*)spec + ((int64_t)(f_ok ? f : 0) * p.nspec + mi.spec_off);
+  const int f0 = it.c0 / 2;
+  const int f = f0 + fi;
+  const uint32_t fl = (uint32_t)((f < p.F ? f : p.F - 1) - f0);
+  const int64_t sbase = (int64_t)f0 * p.nspec + mi.spec_off;
+  const __amdgpu_buffer_rsrc_t b_rs =
+      buffer_rsrc((const C2*)spec + sbase, (uint32_t)(((int64_t)p.F * p.nspec - sbase) * (int64_t)sizeof(C2)));
+  const uint32_t b_off = (fl * (uint32_t)p.nspec + (uint32_t)q) * (uint32_t)sizeof(C2);
+  const bool m0 = m == 0;
   const int b_par = q & 1;
 
   V ra[AU][KCH / VN];
   C2 rb[NB];
   auto fetch = [&](int kc) {
+    const uint32_t sa = (uint32_t)kc * a_step;
 #pragma unroll
     for (int a = 0; a < AU; ++a) {
-      const bool ok = a_ok[a] && (kc * NC + a_ch[a] < a_nch[a]);
-      const V* src = (const V*)(tab + a_base[a] + kc * a_step);
 #pragma unroll
-      for (int v = 0; v < KCH / VN; ++v) ra[a][v] = ok ? gload(src + v) : V{};
+      for (int v = 0; v < KCH / VN; ++v) ra[a][v] = rsrc_load<V>(a_par[a] ? t_rs1 : t_rs0, a_off[a] + v * sizeof(V), sa);
     }
+    const uint32_t sb = (uint32_t)kc * (2 * KI) * (uint32_t)sizeof(C2);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int d = 2 * KI * kc + q + TPF * j;  // n - m
-      C2 x = C2{};
-      if (f_ok && m + d <= p.N) x = gload(sp + d);
-      if (m == 0) x.y = 0;
+      C2 x = rsrc_load<C2>(b_rs, b_off + TPF * j * (uint32_t)sizeof(C2), sb);
+      if (m0) x.y = 0;
       rb[j] = x;
     }
   };
@@ -415,11 +435,7 @@ __device__ inline void split2_bf16(float a, float b, uint32_t* hi, uint32_t* lo)
 
 constexpr int BPAD = 8;
 
-// Raw buffer descriptor over `bytes` bytes from `base` (no stride; loads
-// past the range return zero).
-__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
-}
+
 
 // Synthesis in BF16 split precision on a tile of 128 rings x 64 real
 // columns, both parities.  Wave w computes parity w >> 1 on the rows
