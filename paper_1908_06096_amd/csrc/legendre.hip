@@ -279,50 +279,50 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
   const int64_t rowlen = 2 * (int64_t)p.Fp;
   const int nj = (mi.L + KJ - 1) / KJ;
 
-  int x_par[XU], x_rr[XU], x_c[XU];
+  // X unit: (parity, ring row, column vector).  Rings past L read ring
+  // L - 1 (their table rows are the zero padding: steps of KJ rings never
+  // pass L rounded up to ROWPAD), columns past the row (outputs never
+  // stored) are clamped into it, and the Fourier row offsets of the next
+  // step's rings are looked up one step ahead.
+  int x_par[XU], x_rr[XU], x_c[XU], x_cg[XU];
 #pragma unroll
   for (int a = 0; a < XU; ++a) {
     const int u = tid + 256 * a;
     x_c[a] = (u % CS) * VN;
+    x_cg[a] = min(it.c0 + x_c[a], 2 * p.Fp - VN);
     x_rr[a] = (u / CS) % KJ;
     x_par[a] = u / (CS * KJ);
   }
-  const bool x_cok = true;  // every column read stays inside its 2 Fp row
-  int64_t t_base[TU];
+  // table unit: (parity, chunk, ring row) through one descriptor per parity
+  // (the parity is the same across a wave); chunks past the table read zero
   int t_par[TU], t_ch[TU], t_rr[TU];
-  bool t_ok[TU];
+  uint32_t t_off[TU];
 #pragma unroll
   for (int a = 0; a < TU; ++a) {
     const int u = tid + 256 * a;
-    t_rr[a] = u % KJ;
+    t_par[a] = __builtin_amdgcn_readfirstlane(u / (KJ * NCH));
     t_ch[a] = (u / KJ) % NCH;
-    t_par[a] = u / (KJ * NCH);
-    const int kch = it.t0 / KCH + t_ch[a];
-    const int kp = t_par[a] ? mi.Kp[1] : mi.Kp[0];
-    t_ok[a] = kch * KCH < kp;
-    t_base[a] = (t_par[a] ? mi.toff[1] : mi.toff[0]) + (int64_t)kch * mi.Lp * KCH + (int64_t)t_rr[a] * KCH;
+    t_rr[a] = u % KJ;
+    t_off[a] = ((uint32_t)(it.t0 / KCH + t_ch[a]) * mi.Lp + (uint32_t)t_rr[a]) * (KCH * (uint32_t)sizeof(T));
   }
+  const __amdgpu_buffer_rsrc_t t_rs0 = buffer_rsrc(tab + mi.toff[0], (uint32_t)mi.Kp[0] * mi.Lp * (uint32_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t t_rs1 = buffer_rsrc(tab + mi.toff[1], (uint32_t)mi.Kp[1] * mi.Lp * (uint32_t)sizeof(T));
 
+  int64_t fr[XU], fr_next[XU];
+  auto fetch_rows = [&](int jc, int64_t* dst) {
+#pragma unroll
+    for (int a = 0; a < XU; ++a) dst[a] = gload(&p.rings[mi.first_ring + min(jc * KJ + x_rr[a], mi.L - 1)].frow);
+  };
   V rx[XU];
   V rt[TU][KCH / VN];
   auto fetch = [&](int jc) {
-    const int r0 = jc * KJ;
 #pragma unroll
-    for (int a = 0; a < XU; ++a) {
-      const int r = r0 + x_rr[a];
-      V v = V{};
-      const int c = it.c0 + x_c[a];
-      if (r < mi.L && c < 2 * p.Fp && x_cok) {
-        const int64_t fr = gload(p.rings + mi.first_ring + r).frow;
-        v = gload((const V*)(four + ((fr + m) * 2 + x_par[a]) * rowlen + c));
-      }
-      rx[a] = v;
-    }
+    for (int a = 0; a < XU; ++a) rx[a] = gload((const V*)(four + ((fr[a] + m) * 2 + x_par[a]) * rowlen + x_cg[a]));
+    const uint32_t so = (uint32_t)jc * KJ * KCH * (uint32_t)sizeof(T);
 #pragma unroll
     for (int a = 0; a < TU; ++a) {
-      const V* src = (const V*)(tab + t_base[a] + (int64_t)r0 * KCH);
 #pragma unroll
-      for (int v = 0; v < KCH / VN; ++v) rt[a][v] = t_ok[a] ? gload(src + v) : V{};
+      for (int v = 0; v < KCH / VN; ++v) rt[a][v] = rsrc_load<V>(t_par[a] ? t_rs1 : t_rs0, t_off[a] + v * sizeof(V), so);
     }
   };
 
@@ -334,7 +334,9 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
 #pragma unroll
       for (int j = 0; j < IK; ++j) acc[par][i][j] = acc_t{0, 0, 0, 0};
 
+  fetch_rows(0, fr);
   fetch(0);
+  if (nj > 1) fetch_rows(1, fr_next);
   for (int jc = 0; jc < nj; ++jc) {
 #pragma unroll
     for (int a = 0; a < XU; ++a) *(V*)&Xs[x_par[a]][x_rr[a]][x_c[a]] = rx[a];
@@ -343,7 +345,12 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
 #pragma unroll
       for (int v = 0; v < KCH / VN; ++v) *(V*)&Ts[t_par[a]][t_rr[a]][t_ch[a] * KCH + v * VN] = rt[a][v];
     __syncthreads();
-    if (jc + 1 < nj) fetch(jc + 1);
+    if (jc + 1 < nj) {
+#pragma unroll
+      for (int a = 0; a < XU; ++a) fr[a] = fr_next[a];
+      fetch(jc + 1);
+      if (jc + 2 < nj) fetch_rows(jc + 2, fr_next);
+    }
 #pragma unroll
     for (int par = 0; par < 2; ++par) {
 #pragma unroll
