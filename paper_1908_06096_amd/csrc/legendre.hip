@@ -24,9 +24,12 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // Raw buffer descriptor over `bytes` bytes from `base` (no stride; loads
 // past the range return zero), and 8- / 16-byte loads through one with a
-// lane offset and a uniform offset (bytes).
-__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+// lane offset and a uniform offset (bytes).  The range field is 32 bits:
+// longer arrays get the largest range, which is exact wherever a read can
+// pass the end (offsets are kept within 4 GB of the base by the callers).
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint64_t bytes) {
+  const uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
 }
 template <typename V>
 __device__ __forceinline__ V rsrc_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -151,7 +154,7 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
   const uint32_t fl = (uint32_t)((f < p.F ? f : p.F - 1) - f0);
   const int64_t sbase = (int64_t)f0 * p.nspec + mi.spec_off;
   const __amdgpu_buffer_rsrc_t b_rs =
-      buffer_rsrc((const C2*)spec + sbase, (uint32_t)(((int64_t)p.F * p.nspec - sbase) * (int64_t)sizeof(C2)));
+      buffer_rsrc((const C2*)spec + sbase, (uint64_t)((int64_t)p.F * p.nspec - sbase) * sizeof(C2));
   const uint32_t b_off = (fl * (uint32_t)p.nspec + (uint32_t)q) * (uint32_t)sizeof(C2);
   const bool m0 = m == 0;
   const int b_par = q & 1;
@@ -500,12 +503,15 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
     a_off[a] = ((uint32_t)((2 * a + (tid >> 7)) & 3) * mi.Lp + (uint32_t)(it.t0 + a_row)) * KCH * 2;
   // spectral values: lane fi = tid & 31 is the field, sg = tid >> 5 the
   // segment of 8 consecutive n - m (both parities) within the step
+  // (the descriptor starts at the tile's first field, so offsets stay small)
   const int fi = tid & 31, sg = tid >> 5;
-  const int f = it.c0 / 2 + fi;
-  const uint32_t fc = (uint32_t)(f < p.F ? f : p.F - 1);
+  const int f0 = it.c0 / 2;
+  const int f = f0 + fi;
+  const uint32_t fl = (uint32_t)((f < p.F ? f : p.F - 1) - f0);
+  const int64_t sbase = (int64_t)f0 * p.nspec + mi.spec_off;
   const __amdgpu_buffer_rsrc_t sr =
-      buffer_rsrc((const float2*)spec + mi.spec_off, (uint32_t)(((uint64_t)p.F * p.nspec - mi.spec_off) * 8));
-  const uint32_t b_off = (fc * (uint32_t)p.nspec + 8u * sg) * 8u;
+      buffer_rsrc((const float2*)spec + sbase, (uint64_t)((int64_t)p.F * p.nspec - sbase) * 8u);
+  const uint32_t b_off = (fl * (uint32_t)p.nspec + 8u * sg) * 8u;
   const bool m0 = m == 0;
 
   uint4 ra[AU];

@@ -1,5 +1,5 @@
-"""Parity at the full configured sizes (TCo1279 O1280 x 411 fields in FP32
-and bf16x3, T399 full 400 x 800 x 411 in FP64), with the plans and launches
+"""Parity at the full configured sizes (TCo1279 O1280 x 411 fields in FP32,
+bf16x3 and FP64, T399 full 400 x 800 x 411 in FP64), with the plans and launches
 the benchmark times, on outputs the oracle computes one by one: sampled
 rings of the synthesis, sampled wavenumbers of the analysis, for fields at
 the start, middle and ragged end of the field range.  The inputs are 4
@@ -19,6 +19,7 @@ pytestmark = pytest.mark.gpu
 CASES = [
     (1279, "octahedral", 411, "fp32"),
     (1279, "octahedral", 411, "bf16x3"),
+    (1279, "octahedral", 411, "fp64"),  # spectral array past 4 GB (32-bit load ranges)
     (399, "full", 411, "fp64"),
 ]
 FIELDS = [0, 205, 410]
