@@ -49,14 +49,24 @@ __device__ inline C cscale(C a, T s) {
   return C{a.x * s, a.y * s};
 }
 
-// LDS slot of FFT element i: one spare slot after every 2^FFT_PAD_SHIFT
-// elements.  The early Stockham passes write with a lane stride of R
-// elements (R Ns with Ns < 64), which unpadded would put most lanes of a
-// wave on the same banks; the spare slots spread them.  A transform of L
-// elements spans lds_span(L) slots.
+// LDS layout of the transforms.  The FFT kernels have no LDS but their
+// dynamic buffer, which therefore starts at LDS address 0 (checked on the
+// host).  Element y of that buffer, counted over the whole work group,
+// sits in slot y + y / 32: one spare slot after every 32 elements.  The
+// early Stockham passes write with a lane stride of R elements (R Ns with
+// Ns < 64), which unpadded would put most lanes of a wave on the same
+// banks; the spare slots spread them.  Field s of a work group owns the
+// elements [s fs, s fs + L), fs = lds_stride(L) a multiple of 32, so the byte
+// address of any element is (y + (y >> 5)) * sizeof(C), two instructions
+// from its index.
 constexpr int FFT_PAD_SHIFT = 5;
-__host__ __device__ constexpr int lds_ix(int i) { return i + (i >> FFT_PAD_SHIFT); }
-__host__ __device__ constexpr int lds_span(int L) { return lds_ix(L - 1) + 1; }
+__host__ __device__ constexpr uint32_t lds_stride(int L) { return ((uint32_t)L + 31u) & ~31u; }
+// slots that hold the elements [0, n)
+__host__ __device__ constexpr size_t lds_slots(size_t n) { return n + (n >> FFT_PAD_SHIFT) + 1; }
+template <typename C>
+__device__ __forceinline__ SHT_LDS C* lds_elem(uint32_t y) {
+  return (SHT_LDS C*)((y + (y >> FFT_PAD_SHIFT)) * (uint32_t)sizeof(C));
+}
 
 // 8- and 16-byte values in LDS through an address-space-3 pointer (32-bit
 // addresses), and from a table through a raw buffer descriptor whose range
@@ -288,7 +298,7 @@ enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2, OUT_GRID = 3, OUT_GRI
 // are allocated for it alone.  Every thread of the work group calls it (the
 // barriers).
 template <typename T, int R, int MODE>
-__device__ __noinline__ void stockham_pass(SHT_LDS typename V2T<T>::type* buf, int L, int Ns,
+__device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                            typename V2T<T>::type* io, int h, int lt, int nt) {
   typedef typename V2T<T>::type C;
@@ -309,7 +319,7 @@ __device__ __noinline__ void stockham_pass(SHT_LDS typename V2T<T>::type* buf, i
     kk[i] = Ns > 1 ? b - (int)__umulhi((uint32_t)b, magic) * Ns : 0;
     if (b < nb) {
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = lds_load(buf + lds_ix(b + r * nb));
+      for (int r = 0; r < R; ++r) v[i][r] = lds_load(lds_elem<C>(e0 + (uint32_t)(b + r * nb)));
       if (Ns > 1) {
         const uint32_t t = (uint32_t)(kk[i] * (R - 1)) * (uint32_t)sizeof(C);
 #pragma unroll
@@ -330,11 +340,11 @@ __device__ __noinline__ void stockham_pass(SHT_LDS typename V2T<T>::type* buf, i
         const int o = d + r * Ns;
         const uint32_t ao = (uint32_t)o * (uint32_t)sizeof(C);
         if constexpr (MODE == OUT_PLAIN) {
-          lds_store(buf + lds_ix(o), v[i][r]);
+          lds_store(lds_elem<C>(e0 + (uint32_t)o), v[i][r]);
         } else if constexpr (MODE == OUT_KHAT) {
-          lds_store(buf + lds_ix(o), cconj(cmul(v[i][r], buffer_load<C>(ars, ao))));
+          lds_store(lds_elem<C>(e0 + (uint32_t)o), cconj(cmul(v[i][r], buffer_load<C>(ars, ao))));
         } else if constexpr (MODE == OUT_CHIRP) {
-          if (o < h) lds_store(buf + lds_ix(o), cmul(buffer_load<C>(ars, ao), cconj(v[i][r])));
+          if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), cmul(buffer_load<C>(ars, ao), cconj(v[i][r])));
         } else if constexpr (MODE == OUT_GRID) {
           if (io && o < h) gstore(io + o, cconj(v[i][r]));
         } else {
@@ -347,10 +357,10 @@ __device__ __noinline__ void stockham_pass(SHT_LDS typename V2T<T>::type* buf, i
 }
 
 template <typename T, int MODE>
-__device__ __forceinline__ void pass_dispatch(int R, SHT_LDS typename V2T<T>::type* buf, int L, int Ns,
+__device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
                                      const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                      typename V2T<T>::type* io, int h, int lt, int nt) {
-#define SHT_PASS(RR) stockham_pass<T, RR, MODE>(buf, L, Ns, tw, aux, io, h, lt, nt)
+#define SHT_PASS(RR) stockham_pass<T, RR, MODE>(e0, L, Ns, tw, aux, io, h, lt, nt)
   switch (R) {
     case 20: SHT_PASS(20); break;
     case 18: SHT_PASS(18); break;
@@ -372,35 +382,35 @@ __device__ __forceinline__ void pass_dispatch(int R, SHT_LDS typename V2T<T>::ty
 // Forward DFT of L points held in LDS (natural order in and out); the last
 // pass applies MODE with aux and io.
 template <typename T, int MODE>
-__device__ __forceinline__ void fft_lds(SHT_LDS typename V2T<T>::type* buf, int L, int nrad, const int32_t* rad,
+__device__ __forceinline__ void fft_lds(uint32_t e0, int L, int nrad, const int32_t* rad,
                                         const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                         typename V2T<T>::type* io, int h, int lt, int nt) {
   int Ns = 1;
   for (int q = 0; q < nrad; ++q) {
     const int R = gload(rad + q);
-    if (q == nrad - 1) pass_dispatch<T, MODE>(R, buf, L, Ns, tw, aux, io, h, lt, nt);
-    else pass_dispatch<T, OUT_PLAIN>(R, buf, L, Ns, tw, nullptr, nullptr, h, lt, nt);
+    if (q == nrad - 1) pass_dispatch<T, MODE>(R, e0, L, Ns, tw, aux, io, h, lt, nt);
+    else pass_dispatch<T, OUT_PLAIN>(R, e0, L, Ns, tw, nullptr, nullptr, h, lt, nt);
     tw += Ns * (R - 1);
     Ns *= R;
   }
 }
 
 // Forward complex DFT of length h.  Input: z_t, t < h, in LDS at
-// buf[lds_ix(t)], multiplied by the chirp c_t for chirp-z classes, whose
-// entries h <= t < L must be zero.  Output: Z_q, q < h, in LDS at
-// buf[lds_ix(q)], or with GRID_OUT its conjugate written to io (nothing
+// element e0 + t, multiplied by the chirp c_t for chirp-z classes, whose
+// entries h <= t < L must be zero.  Output: Z_q, q < h, in LDS at element
+// e0 + q, or with GRID_OUT its conjugate written to io (nothing
 // when io is null).  Chirp-z: A = DFT_L(a), B = conj(A khat),
 // Z_q = c_q conj(DFT_L(B))_q.
 template <typename T, bool GRID_OUT>
-__device__ __forceinline__ void dft_h(SHT_LDS typename V2T<T>::type* buf, const FftClass& c, const int32_t* rad,
+__device__ __forceinline__ void dft_h(uint32_t e0, const FftClass& c, const int32_t* rad,
                       const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
   if (!c.bluestein) {
-    fft_lds<T, GRID_OUT ? OUT_GRID : OUT_PLAIN>(buf, c.L, c.nrad, rad, tw, nullptr, io, c.h, lt, nt);
+    fft_lds<T, GRID_OUT ? OUT_GRID : OUT_PLAIN>(e0, c.L, c.nrad, rad, tw, nullptr, io, c.h, lt, nt);
     return;
   }
-  fft_lds<T, OUT_KHAT>(buf, c.L, c.nrad, rad, tw, tabs + c.khat_off, nullptr, c.h, lt, nt);
-  fft_lds<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP>(buf, c.L, c.nrad, rad, tw, tabs + c.chirp_off, io, c.h, lt, nt);
+  fft_lds<T, OUT_KHAT>(e0, c.L, c.nrad, rad, tw, tabs + c.khat_off, nullptr, c.h, lt, nt);
+  fft_lds<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP>(e0, c.L, c.nrad, rad, tw, tabs + c.chirp_off, io, c.h, lt, nt);
 }
 
 // Sweeps over a ring (gathers, scatters) issue the global loads of
@@ -415,7 +425,7 @@ size_t fft_grid_blocks(int nitems) { return (size_t)nitems; }
 //   X_m = c_m for m <= mmax_j (Im c_0 dropped), 0 above, Nyquist 0;
 //   Z_q = (X_q + conj X_{h-q}) + i w^q (X_q - conj X_{h-q}),  w = exp(2 pi i / n);
 //   z = inverse DFT_h(Z) = conj(DFT_h(conj Z));  g_{2t} = Re z_t,  g_{2t+1} = Im z_t.
-// Field f0 + s owns LDS slots [s S, (s + 1) S), S = lds_span(L), and threads
+// Field f0 + s owns the LDS elements [s fs, s fs + L), fs = lds_stride(L), and threads
 // [s nt, (s + 1) nt).
 // The gather of X reads element e as (q = e / G, s = e mod G), so that
 // neighbouring lanes read neighbouring fields of one Fourier row.
@@ -425,12 +435,10 @@ template <typename T>
 __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int fb, int fend,
                                                 const T* __restrict__ four, T* __restrict__ grid) {
   typedef typename V2T<T>::type C;
-  extern __shared__ __align__(16) unsigned char smem[];
   const RingInfo ri = gload(p.rings + ring);
   const FftClass cl = gload(p.classes + ri.cls);
   const int32_t* rad = p.classes[ri.cls].rad;
   const C* tabs = (const C*)p.fft;
-  C* buf = (C*)smem;
   const C* post = tabs + cl.post_off;
   const C* chirp = tabs + cl.chirp_off;
   const C* fc = (const C*)four;
@@ -440,7 +448,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
   const int gs = cl.gshift, G = 1 << gs;
   const int nt = FFT_THREADS >> gs;
   const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
-  const int S = lds_span(L);
+  const uint32_t fs = lds_stride(L);
   {
     // Z_q and Z_{h-q} are built from the same two coefficients X_q and
     // X_{h-q}, so pair p = q (0 <= q <= h/2) loads them once and writes both
@@ -476,7 +484,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
             const C t = cmul(cconj(pa[u]), csub(A, xr));
             C y = C{sm.x - t.y, -(sm.y + t.x)};  // conj(sm + i t)
             if (blue) y = cmul(y, ca[u]);
-            buf[s * S + lds_ix(q)] = y;
+            lds_store(lds_elem<C>(s * fs + q), y);
           }
           if (q >= 1 && q2 != q) {
             // Z_{h-q} from X_{h-q} = B and conj X_q = conj A
@@ -485,7 +493,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
             const C t = cmul(cconj(pb[u]), csub(B, xr));
             C y = C{sm.x - t.y, -(sm.y + t.x)};
             if (blue) y = cmul(y, cb[u]);
-            buf[s * S + lds_ix(q2)] = y;
+            lds_store(lds_elem<C>(s * fs + q2), y);
           }
         }
       }
@@ -495,7 +503,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
       const int nz = (L - h) << gs;
       for (int e = threadIdx.x; e < nz; e += FFT_THREADS) {
         const int s = e & (G - 1), t = h + (e >> gs);
-        buf[s * S + lds_ix(t)] = C{0, 0};
+        lds_store(lds_elem<C>(s * fs + t), C{0, 0});
       }
     }
     __syncthreads();
@@ -503,7 +511,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
     const int f = fb + sub;
     C* g = f < fend ? (C*)(grid + (int64_t)f * p.npts + ri.goff) : nullptr;
     // the last pass writes the grid (the conjugate of the inverse transform)
-    dft_h<T, true>((SHT_LDS C*)(buf + sub * S), cl, rad, tabs, g, lt, nt);
+    dft_h<T, true>(sub * fs, cl, rad, tabs, g, lt, nt);
   }
 }
 
@@ -521,7 +529,6 @@ template <typename T>
 __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int fb, int fend,
                                                const T* __restrict__ grid, T* __restrict__ four) {
   typedef typename V2T<T>::type C;
-  extern __shared__ __align__(16) unsigned char smem[];
   const RingInfo rn = gload(p.rings + ring);
   const RingInfo rs = gload(p.rings + rn.mirror);
   const FftClass cl = gload(p.classes + rn.cls);
@@ -529,9 +536,8 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   const C* tabs = (const C*)p.fft;
   const int h = cl.h, mmax = rn.mmax, L = cl.L;
   const int gs = cl.gshift, G = 1 << gs;
-  C* buf = (C*)smem;
-  const int S = lds_span(L);
-  C* keep = buf + G * S;
+  const uint32_t fs = lds_stride(L);
+  const uint32_t keep = G * fs;  // first element of the north results
   const C* post = tabs + cl.post_off;
   const C* chirp = tabs + cl.chirp_off;
   C* fc = (C*)four;
@@ -544,7 +550,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   {
     const int f = fb + sub;
     for (int side = 0; side < 2; ++side) {
-      C* dst = buf + sub * S;
+      const uint32_t dst = sub * fs;
       const C* g = (const C*)(grid + (int64_t)min(f, fend - 1) * p.npts + (side ? rs.goff : rn.goff));
       for (int t0 = lt; t0 < Q; t0 += FFT_SWEEP * nt) {
         C z[FFT_SWEEP], c[FFT_SWEEP];
@@ -558,11 +564,11 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
 #pragma unroll
         for (int u = 0; u < FFT_SWEEP; ++u) {
           const int t = t0 + u * nt;
-          if (t < Q) dst[lds_ix(t)] = blue ? cmul(z[u], c[u]) : z[u];
+          if (t < Q) lds_store(lds_elem<C>(dst + t), blue ? cmul(z[u], c[u]) : z[u]);
         }
       }
       __syncthreads();
-      dft_h<T, false>((SHT_LDS C*)dst, cl, rad, tabs, nullptr, lt, nt);
+      dft_h<T, false>(dst, cl, rad, tabs, nullptr, lt, nt);
       const int nm = M << gs;
       for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * FFT_THREADS) {
         C pm[FFT_SWEEP];
@@ -576,9 +582,8 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
           const int e = e0 + u * FFT_THREADS;
           if (e >= nm) continue;
           const int s = e & (G - 1), m = e >> gs;
-          const C* z = buf + s * S;
-          const C zm = z[lds_ix(m)];
-          const C zr = cconj(z[lds_ix(m == 0 ? 0 : h - m)]);
+          const C zm = lds_load(lds_elem<C>(s * fs + m));
+          const C zr = cconj(lds_load(lds_elem<C>(s * fs + (m == 0 ? 0 : h - m))));
           const C sm = cadd(zm, zr);
           const C d = csub(zm, zr);
           const C t = cmul(pm[u], d);
@@ -587,9 +592,9 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
           if (m == 0) x = C{zm.x + zm.y, 0};
           x = cscale(x, scale);
           if (side == 0) {
-            keep[s * M + m] = x;
+            lds_store(lds_elem<C>(keep + s * M + m), x);
           } else if (fb + s < fend) {
-            const C xn = keep[s * M + m];
+            const C xn = lds_load(lds_elem<C>(keep + s * M + m));
             C* row = fc + ((rn.frow + m) * 2) * (int64_t)p.Fp + fb + s;
             gstore(row, cadd(xn, x));
             gstore(row + p.Fp, csub(xn, x));
@@ -603,7 +608,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
 
 size_t fft_lds_bytes(int prec, int L, int mmax, int G) {
   const size_t c = (prec == SHT_FP64) ? 16 : 8;
-  return c * (size_t)G * ((size_t)lds_span(L) + (mmax >= 0 ? (size_t)mmax + 1 : 0));
+  return c * lds_slots((size_t)G * (lds_stride(L) + (mmax >= 0 ? (size_t)mmax + 1 : 0)));
 }
 
 // Kernels: work groups loop over the items (grid stride).  FP32 kernels are
@@ -670,15 +675,20 @@ int fft_blocks_per_cu(int prec, size_t lds) {
   return n;
 }
 
+// Every FFT kernel addresses its dynamic LDS buffer from LDS address 0,
+// which holds only while the kernels declare no LDS of their own.
 hipError_t fft_set_max_lds(size_t bytes) {
-  hipError_t e;
-  e = hipFuncSetAttribute((const void*)fourier_synthesis_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)fourier_synthesis_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)fourier_analysis_kernel<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)fourier_analysis_kernel<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  const void* kernels[] = {(const void*)fourier_synthesis_kernel<double>, (const void*)fourier_synthesis_kernel<float>,
+                           (const void*)fourier_analysis_kernel<double>, (const void*)fourier_analysis_kernel<float>};
+  for (const void* f : kernels) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, f);
+    if (e != hipSuccess) return e;
+    if (a.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace shtmi
