@@ -31,6 +31,16 @@ __device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint64_t 
   const uint32_t n = bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes;
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n, 0x00020000);
 }
+// The same over a base and range that are the same on every lane, read
+// from the first lane so that the descriptor provably sits in scalar
+// registers (instructions that need it there otherwise loop over lanes).
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc_uniform(const void* base, uint64_t bytes) {
+  const uint64_t a = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)a);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(a >> 32));
+  const uint32_t n = __builtin_amdgcn_readfirstlane(bytes > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(((uint64_t)hi << 32) | lo), (short)0, (int)n, 0x00020000);
+}
 template <typename V>
 __device__ __forceinline__ V rsrc_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
   static_assert(sizeof(V) == 8 || sizeof(V) == 16, "8- or 16-byte values");
@@ -458,21 +468,24 @@ constexpr int BPAD = 8;
 // LDS operand layout [parity][plane][k chunk of 8][row or column] x 8 k:
 // a lane's operand (8 consecutive k of one row or column) is one 16-byte
 // read, and 8 lanes reading 8 consecutive rows touch distinct banks.
-// Table units (16 bytes: 8 k of one ring) and spectral values are loaded
-// without branches (clamped indices, zeros selected) one step ahead.
+// The table stages are copied into LDS one step ahead (two stage buffers);
+// the spectral values are loaded into registers one step ahead (clamped
+// field index, zeros selected) and split into the one spectral stage.
 constexpr int BF_BM = 128, BF_BN = 64, BF_KI = 32;
 
 __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const WorkItem it, const float* __restrict__ spec,
                                                     float* __restrict__ four) {
   constexpr int BM = BF_BM, BN = BF_BN, KI = BF_KI;
-  constexpr int NCK = KI / KCH;              // k chunks per parity per step
-  constexpr int AU = 2 * 2 * NCK * BM / 256; // table units per thread
-  constexpr int FROW = BN + 4;               // epilogue exchange row (floats)
-  static_assert(AU == 8 && BN == 64 && BM * FROW * 4 <= 2 * 2 * NCK * (BM + BN) * 16, "tile shape");
-  __shared__ __align__(16) uint4 smem[2 * 2 * NCK * (BM + BN)];
-  uint4* As = smem;                          // [par][plane][chunk][BM]
-  uint4* Bs = smem + 2 * 2 * NCK * BM;       // [par][plane][chunk][BN]
-  float* Xs = (float*)smem;                  // epilogue: A parity [BM][FROW]
+  constexpr int NCK = KI / KCH;         // k chunks per parity per step
+  constexpr int AS = 2 * 2 * NCK * BM;  // 16-byte units of one table stage
+  constexpr int BS = 2 * 2 * NCK * BN;  // 16-byte units of the spectral stage
+  constexpr int FROW = BN + 4;          // epilogue exchange row (floats)
+  static_assert(BM == 128 && BN == 64 && BM * FROW * 4 <= 2 * AS * 16, "tile shape");
+  // two table stages [par][plane][chunk][BM], then the spectral stage
+  // [par][plane][chunk][BN]; 80 KB, two work groups per CU
+  __shared__ __align__(16) uint4 smem[2 * AS + BS];
+  uint4* Bs = smem + 2 * AS;
+  float* Xs = (float*)smem;  // epilogue: A parity [BM][FROW]
 
   const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
@@ -488,19 +501,30 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
   // padded k range return zero, so spectral values read past n = N (the
   // next wavenumber's, or zeros past the end) meet zero table entries, and
   // rows past the table or fields past F only feed outputs never stored.
-  // Table unit a = tid + 256 a holds row tid % 128 of chunk (2a + tid / 128) % 4,
-  // plane (a / 2) % 2, parity a / 4 (so its descriptor is uniform).
   const u16* tab = (const u16*)p.tab;
-  const int a_row = tid & (BM - 1);
-  const __amdgpu_buffer_rsrc_t t00 = buffer_rsrc(tab + mi.toff[0], (uint32_t)mi.Kp[0] * mi.Lp * 2);
-  const __amdgpu_buffer_rsrc_t t01 = buffer_rsrc(tab + p.tab_plane + mi.toff[0], (uint32_t)mi.Kp[0] * mi.Lp * 2);
-  const __amdgpu_buffer_rsrc_t t10 = buffer_rsrc(tab + mi.toff[1], (uint32_t)mi.Kp[1] * mi.Lp * 2);
-  const __amdgpu_buffer_rsrc_t t11 = buffer_rsrc(tab + p.tab_plane + mi.toff[1], (uint32_t)mi.Kp[1] * mi.Lp * 2);
-  const uint32_t a_step = (uint32_t)NCK * mi.Lp * KCH * 2;  // bytes per step
-  uint32_t a_off[AU];
+  const uint32_t a_step = __builtin_amdgcn_readfirstlane((uint32_t)NCK * mi.Lp * KCH * 2);  // bytes per step
+  // Table stages are copied from memory straight into LDS, 16 bytes a lane:
+  // one copy fills 1 KB at a wave-uniform LDS address with 64 consecutive
+  // table units (8 k of 64 consecutive rings, contiguous in the table's
+  // chunk-major layout).  Wave w copies parity w / 2, plane w % 2: NCK
+  // chunks times two 64-row halves per step.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int cpar = wv >> 1, cpl = wv & 1;
+  const __amdgpu_buffer_rsrc_t tr = buffer_rsrc_uniform(tab + (cpl ? p.tab_plane : 0) + mi.toff[cpar],
+                                                        (uint64_t)mi.Kp[cpar] * mi.Lp * 2);
+  const uint32_t t_lane = (uint32_t)(it.t0 + lane) * KCH * 2;
+  auto fetch_table = [&](int kc, int stage) {
+    const uint32_t sa = (uint32_t)kc * a_step;
 #pragma unroll
-  for (int a = 0; a < AU; ++a)
-    a_off[a] = ((uint32_t)((2 * a + (tid >> 7)) & 3) * mi.Lp + (uint32_t)(it.t0 + a_row)) * KCH * 2;
+    for (int ch = 0; ch < NCK; ++ch) {
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        SHT_LDS void* dst = (SHT_LDS void*)(smem + stage * AS + ((cpar * 2 + cpl) * NCK + ch) * BM + 64 * hf);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(tr, dst, 16, t_lane + (uint32_t)(ch * mi.Lp + 64 * hf) * KCH * 2,
+                                                 sa, 0, 0);
+      }
+    }
+  };
   // spectral values: lane fi = tid & 31 is the field, sg = tid >> 5 the
   // segment of 8 consecutive n - m (both parities) within the step
   // (the descriptor starts at the tile's first field, so offsets stay small)
@@ -510,27 +534,17 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
   const uint32_t fl = (uint32_t)((f < p.F ? f : p.F - 1) - f0);
   const int64_t sbase = (int64_t)f0 * p.nspec + mi.spec_off;
   const __amdgpu_buffer_rsrc_t sr =
-      buffer_rsrc((const float2*)spec + sbase, (uint64_t)((int64_t)p.F * p.nspec - sbase) * 8u);
+      buffer_rsrc_uniform((const float2*)spec + sbase, (uint64_t)((int64_t)p.F * p.nspec - sbase) * 8u);
   const uint32_t b_off = (fl * (uint32_t)p.nspec + 8u * sg) * 8u;
   const bool m0 = m == 0;
 
-  uint4 ra[AU];
-  float2 rb[8];
-  auto fetch = [&](int kc) {
-    const uint32_t sa = (uint32_t)kc * a_step;
-#pragma unroll
-    for (int a = 0; a < AU; ++a) {
-      const int pa = a >> 2, pl = (a >> 1) & 1;
-      const __amdgpu_buffer_rsrc_t r = pa ? (pl ? t11 : t10) : (pl ? t01 : t00);
-      ra[a] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, a_off[a], sa, 0));
-    }
+  // (raw loads only: anything computed from them here would wait for them)
+  float4 rv[4];
+  auto fetch_spec = [&](int kc) {
     const uint32_t sb = (uint32_t)kc * (2 * KI * 8);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const float4 v = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off + 16 * q, sb, 0));
-      rb[2 * q] = make_float2(v.x, m0 ? 0.f : v.y);
-      rb[2 * q + 1] = make_float2(v.z, m0 ? 0.f : v.w);
-    }
+    for (int q = 0; q < 4; ++q)
+      rv[q] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off + 16 * q, sb, 0));
   };
 
   f32x4 acc[4][4];
@@ -539,15 +553,18 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0, 0, 0, 0};
 
-  fetch(0);
+  fetch_table(0, 0);
+  fetch_spec(0);
   for (int kc = 0; kc < nk; ++kc) {
-#pragma unroll
-    for (int a = 0; a < AU; ++a) {
-      const int pa = a >> 2, pl = (a >> 1) & 1, ch = (2 * a + (tid >> 7)) & 3;
-      As[((pa * 2 + pl) * NCK + ch) * BM + a_row] = ra[a];
-    }
     // element i of the segment: parity i & 1, k = 4 sg + i / 2 within the step
-    // (chunk sg / 2, offset 4 (sg & 1)); columns 2 fi (re) and 2 fi + 1 (im)
+    // (chunk sg / 2, offset 4 (sg & 1)); columns 2 fi (re) and 2 fi + 1 (im);
+    // Im a_n^0 is dropped
+    float2 rb[8];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      rb[2 * q] = make_float2(rv[q].x, m0 ? 0.f : rv[q].y);
+      rb[2 * q + 1] = make_float2(rv[q].z, m0 ? 0.f : rv[q].w);
+    }
 #pragma unroll
     for (int pa = 0; pa < 2; ++pa) {
 #pragma unroll
@@ -565,8 +582,15 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
         *dl = make_uint2(l[0], l[1]);
       }
     }
+    // this wave's table copies for step kc have landed; after the barrier
+    // every wave's have
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
-    if (kc + 1 < nk) fetch(kc + 1);
+    if (kc + 1 < nk) {
+      fetch_table(kc + 1, (kc + 1) & 1);
+      fetch_spec(kc + 1);
+    }
+    const uint4* As = smem + (kc & 1) * AS;
     uint4 bh[4], bl[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -586,8 +610,13 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
         acc[i][j] = mfma_bf16(ah, bh[j], acc[i][j]);
       }
     }
-    __syncthreads();
+    // every wave's LDS reads of this step are done before the next step
+    // overwrites the spectral stage (and, a step later, this table stage);
+    // the table copies in flight are waited for where they are used, not
+    // here (a __syncthreads would wait for them too)
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
   }
+  __syncthreads();
 
   // epilogue: the parity-1 waves hand A to the parity-0 waves through LDS;
   // element (i, j, e): row 64 rh + 16 i + 4 (lane / 16) + e, column 16 j + lane % 16
@@ -835,7 +864,7 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(const DevPlan* 
   }
 }
 
-__global__ __launch_bounds__(256) void legendre_inverse_bf16x3_kernel(const DevPlan* __restrict__ plans,
+__global__ __launch_bounds__(256, 2) void legendre_inverse_bf16x3_kernel(const DevPlan* __restrict__ plans,
                                                                       const WorkItem* __restrict__ items, int nitems,
                                                                       const IoBind* __restrict__ io, IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
