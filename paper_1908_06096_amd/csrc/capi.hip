@@ -157,14 +157,17 @@ struct sht_plan_s {
   int elem = 8;
   int variant = TILE_C128;
   std::vector<RingInfo> rings;
-  std::vector<FftClass> classes;
+  std::vector<FftClass> classes;      // synthesis work groups
+  std::vector<FftClass> classes_ana;  // analysis work groups (same lengths and tables)
   std::vector<MInfo> ms;
   std::vector<int64_t> ring_off, four_row;
   std::vector<WorkItem> inv_items, dir_items;
-  std::vector<FftItem> syn_items, ana_items;
+  std::vector<FftItem> syn_items, ana_items;  // tier-0 work groups first
+  int syn_split = 0, ana_split = 0;           // number of tier-0 work groups
   int64_t tab_plane = 0;
   size_t tab_bytes = 0, fft_bytes = 0;
-  size_t lds_syn = 0, lds_ana = 0;
+  size_t lds_syn = 0, lds_ana = 0;            // largest of the tiers'
+  size_t lds_syn_t[FFT_TIERS] = {}, lds_ana_t[FFT_TIERS] = {};
   int max_Lp = 0;
   // device: shared tables, and this plan's own arena (descriptor, work lists)
   std::shared_ptr<SharedTables> tables;
@@ -236,7 +239,8 @@ void legendre_items(const sht_plan_s* p, int variant, int plan, std::vector<Work
   legendre_arrange(dir);
 }
 
-// FFT work items of one plan, longest transforms first.
+// FFT work items (chunks of up to FFT_FCHUNK fields) of one plan, longest
+// transforms first, into the lists of their classes' tiers.
 void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::vector<FftItem>* ana) {
   std::vector<int> order(p->nlat);
   std::iota(order.begin(), order.end(), 0);
@@ -246,8 +250,9 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
   for (int j : order)
     for (int f0 = 0; f0 < p->F; f0 += FFT_FCHUNK) {
       const int fend = std::min(f0 + FFT_FCHUNK, p->F);
-      syn->push_back(FftItem{j, f0, plan, fend});
-      if (j < p->nh) ana->push_back(FftItem{j, f0, plan, fend});
+      const int cls = p->rings[j].cls;
+      syn[p->classes[cls].tier].push_back(FftItem{j, f0, plan, fend});
+      if (j < p->nh) ana[p->classes_ana[cls].tier].push_back(FftItem{j, f0, plan, fend});
     }
 }
 
@@ -259,7 +264,7 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
 // of its eight): they run on one XCD at the same time, and their strided
 // reads and writes of the chunk's Fourier rows (fields are the innermost
 // index) meet in that XCD's L2.
-void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
+void fft_arrange(const sht_plan_t* plans, bool analysis, std::vector<FftItem>* items) {
   std::vector<FftItem> chunks;
   chunks.swap(*items);
   for (size_t c0 = 0; c0 < chunks.size(); c0 += NUM_XCD) {
@@ -268,7 +273,7 @@ void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
     for (int k = 0; k < nc; ++k) {
       const FftItem& c = chunks[c0 + k];
       const sht_plan_s* p = plans[c.plan];
-      G[k] = p->classes[p->rings[c.ring].cls].G;
+      G[k] = (analysis ? p->classes_ana : p->classes)[p->rings[c.ring].cls].G;
       ng[k] = (c.fend - c.f0 + G[k] - 1) / G[k];
       most = std::max(most, ng[k]);
     }
@@ -283,6 +288,87 @@ void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
         }
       }
   }
+}
+
+// Work-group size and fields per work group of each FFT class for one
+// direction (the analysis also keeps the north ring's mmax + 1 results per
+// field in LDS).  Tier 0 (FFT_THREADS_SMALL threads) where that many threads
+// per field reach the pass count FFT_THREADS threads do, and one field's LDS
+// leaves the small groups' occupancy at what their registers allow (a
+// launch's LDS per group is its largest item's).  G: the most fields (up to
+// FFT_MAX_G) whose threads per field (the tier's work-group size / G) still
+// hold every pass with the same pass count and whose LDS fits the tier's
+// budget, the most LDS that keeps the occupancy the tier's longest class has
+// with G = 1.  A ring of class h carries mmax = min(N, h - 1).  The classes
+// come in with the radices for FFT_THREADS threads per field.
+void choose_groups(int prec, int N, bool analysis, std::vector<FftClass>* cls) {
+  auto lds = [&](const FftClass& c, int G) {
+    return fft_lds_bytes(prec, c.L, analysis ? std::min(N, c.h - 1) : -1, G);
+  };
+  const int full = fft_blocks_per_cu(prec, 0, 0);
+  for (FftClass& c : *cls) {
+    const std::vector<int> rs = radices(c.L, FFT_THREADS_SMALL);
+    c.tier = (!rs.empty() && (int)rs.size() == c.nrad && fft_blocks_per_cu(prec, 0, lds(c, 1)) >= full) ? 0 : 1;
+    if (c.tier == 0)
+      for (size_t q = 0; q < rs.size(); ++q) c.rad[q] = rs[q];
+  }
+  size_t budget[FFT_TIERS];
+  for (int t = 0; t < FFT_TIERS; ++t) {
+    size_t need1 = 0;
+    for (const FftClass& c : *cls)
+      if (c.tier == t) need1 = std::max(need1, lds(c, 1));
+    budget[t] = need1;
+    if (need1 == 0) continue;
+    const int occ = fft_blocks_per_cu(prec, t, need1);
+    for (size_t b = need1 + 1024; b <= 160 * 1024; b += 1024) {
+      if (fft_blocks_per_cu(prec, t, b) < occ) break;
+      budget[t] = b;
+    }
+  }
+  for (FftClass& c : *cls) {
+    const int threads = fft_tier_threads(c.tier);
+    int gs = 0;
+    std::vector<int> best(c.rad, c.rad + c.nrad);
+    for (int s = 0; (2 << s) <= FFT_MAX_G; ++s) {
+      const int G = 2 << s;
+      const std::vector<int> rad = radices(c.L, threads / G);
+      if (rad.empty() || rad.size() > (size_t)c.nrad) break;
+      if (lds(c, G) > budget[c.tier]) break;
+      gs = s + 1;
+      best = rad;
+    }
+    c.G = 1 << gs;
+    c.gshift = gs;
+    for (size_t q = 0; q < best.size(); ++q) c.rad[q] = best[q];
+  }
+}
+
+// The two launches of an FFT stage over a work list whose first `split`
+// work groups belong to tier 0, one work group per list entry.
+hipError_t fft_launch_tiers(bool synthesis, const DevPlan* plans, int prec, const FftItem* items, int n, int split,
+                            const IoBind* io, IoBind io0, const size_t* lds, hipStream_t s) {
+  for (int t = 0; t < FFT_TIERS; ++t) {
+    const int first = t ? split : 0, count = t ? n - split : split;
+    const hipError_t e =
+        synthesis ? launch_fourier_synthesis(plans, prec, t, items + first, count, io, io0, lds[t],
+                                             (int)fft_grid_blocks(count), s)
+                  : launch_fourier_analysis(plans, prec, t, items + first, count, io, io0, lds[t],
+                                            (int)fft_grid_blocks(count), s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// One launch list from per-tier chunk lists (each in launch order): each
+// tier's chunks become its work groups, tier 0 first.  Returns the number of
+// tier-0 work groups.
+int fft_join(const sht_plan_t* plans, bool analysis, std::vector<FftItem>* tiers, std::vector<FftItem>* out) {
+  out->clear();
+  for (int t = 0; t < FFT_TIERS; ++t) fft_arrange(plans, analysis, &tiers[t]);
+  out->insert(out->end(), tiers[0].begin(), tiers[0].end());
+  const int split = (int)out->size();
+  for (int t = 1; t < FFT_TIERS; ++t) out->insert(out->end(), tiers[t].begin(), tiers[t].end());
+  return split;
 }
 
 int build_host(sht_plan_s* p) {
@@ -350,44 +436,32 @@ int build_host(sht_plan_s* p) {
     }
     p->classes.push_back(c);
   }
+  // Work groups of each direction (the analysis keeps more in LDS).  The
+  // twiddle table follows the radix sequence, so an analysis class whose
+  // radices differ from the synthesis' gets a twiddle table of its own.
+  p->classes_ana = p->classes;
+  choose_groups(p->prec, N, false, &p->classes);
+  choose_groups(p->prec, N, true, &p->classes_ana);
+  for (size_t i = 0; i < p->classes.size(); ++i) {
+    const FftClass& c = p->classes[i];
+    FftClass& a = p->classes_ana[i];
+    if (a.nrad != c.nrad || !std::equal(a.rad, a.rad + a.nrad, c.rad)) {
+      a.root_off = off;
+      off += a.L;
+    }
+  }
   p->fft_bytes = (size_t)off * csize;
-  // Fields per work group: the most (up to FFT_MAX_G) whose FFT_THREADS / G
-  // threads still hold every pass and whose LDS fits the budget: the most
-  // LDS that keeps the occupancy the longest class has with G = 1.
-  // A ring of class h carries mmax = min(N, h - 1).
-  size_t need1 = 0;
-  for (const FftClass& c : p->classes)
-    need1 = std::max(need1, fft_lds_bytes(p->prec, c.L, std::min(N, c.h - 1), 1));
-  size_t budget = need1;
-  {
-    const int occ = fft_blocks_per_cu(p->prec, need1);
-    for (size_t b = need1 + 1024; b <= 160 * 1024; b += 1024) {
-      if (fft_blocks_per_cu(p->prec, b) < occ) break;
-      budget = b;
-    }
-  }
-  // A G > 1 must keep the pass count of G = 1 (its radices may differ).
-  for (FftClass& c : p->classes) {
-    int gs = 0;
-    std::vector<int> best(c.rad, c.rad + c.nrad);
-    for (int s = 0; (2 << s) <= FFT_MAX_G; ++s) {
-      const int G = 2 << s;
-      const std::vector<int> rad = radices(c.L, FFT_THREADS / G);
-      if (rad.empty() || rad.size() > (size_t)c.nrad) break;
-      if (fft_lds_bytes(p->prec, c.L, std::min(N, c.h - 1), G) > budget) break;
-      gs = s + 1;
-      best = rad;
-    }
-    c.G = 1 << gs;
-    c.gshift = gs;
-    for (size_t q = 0; q < best.size(); ++q) c.rad[q] = best[q];
-  }
   for (auto& r : p->rings) {
     const int h = r.nlon / 2;
     r.cls = (int)(std::lower_bound(hs.begin(), hs.end(), h) - hs.begin());
-    const FftClass& c = p->classes[r.cls];
-    p->lds_syn = std::max(p->lds_syn, fft_lds_bytes(p->prec, c.L, -1, c.G));
-    p->lds_ana = std::max(p->lds_ana, fft_lds_bytes(p->prec, c.L, r.mmax, c.G));
+    const FftClass& cs = p->classes[r.cls];
+    const FftClass& ca = p->classes_ana[r.cls];
+    size_t& ls = p->lds_syn_t[cs.tier];
+    size_t& la = p->lds_ana_t[ca.tier];
+    ls = std::max(ls, fft_lds_bytes(p->prec, cs.L, -1, cs.G));
+    la = std::max(la, fft_lds_bytes(p->prec, ca.L, r.mmax, ca.G));
+    p->lds_syn = std::max(p->lds_syn, ls);
+    p->lds_ana = std::max(p->lds_ana, la);
   }
   if (p->lds_ana > 160 * 1024) return SHT_EUNSUPPORTED;
 
@@ -425,9 +499,12 @@ int build_host(sht_plan_s* p) {
   // ---- work lists (m ascending = cost descending for both products) ----
   p->variant = default_variant(p->prec, p->F);
   legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
-  fft_items(p, 0, &p->syn_items, &p->ana_items);
-  fft_arrange(&p, &p->syn_items);
-  fft_arrange(&p, &p->ana_items);
+  {
+    std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
+    fft_items(p, 0, st, at);
+    p->syn_split = fft_join(&p, false, st, &p->syn_items);
+    p->ana_split = fft_join(&p, true, at, &p->ana_items);
+  }
   return SHT_OK;
 }
 
@@ -488,7 +565,7 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   };
   const Part parts[] = {
       {&v_rings, sizeof(RingInfo) * p->rings.size()},
-      {&v_cls, sizeof(FftClass) * p->classes.size()},
+      {&v_cls, 2 * sizeof(FftClass) * p->classes.size()},  // synthesis, then analysis classes
       {&v_ms, sizeof(MInfo) * p->ms.size()},
       {&v_mu, sizeof(double) * p->nlat},
       {&v_w, sizeof(double) * p->nlat},
@@ -519,6 +596,7 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   d.nspec = p->nspec;
   d.rings = (const RingInfo*)v_rings;
   d.classes = (const FftClass*)v_cls;
+  d.classes_ana = (const FftClass*)v_cls + p->classes.size();
   d.ms = (const MInfo*)v_ms;
   d.mu = (const double*)v_mu;
   d.w = (const double*)v_w;
@@ -529,14 +607,18 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   p->d_cls = (FftClass*)v_cls;
 
   HIP_TRY(hipMemcpyAsync(v_rings, p->rings.data(), parts[0].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), parts[1].bytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), sizeof(FftClass) * p->classes.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync((FftClass*)v_cls + p->classes.size(), p->classes_ana.data(),
+                         sizeof(FftClass) * p->classes_ana.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(v_ms, p->ms.data(), parts[2].bytes, hipMemcpyHostToDevice, s));
   int rc = build_own(p, s);
   if (rc != SHT_OK) return rc;
 
   HIP_TRY(launch_gauss(p->nlat, (double*)v_mu, (double*)v_w, s));
   HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane, s));
-  HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls, (int)p->classes.size(), p->classes.data(), v_fft, s));
+  HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls, (int)p->classes.size(), p->classes.data(), v_fft, false, s));
+  HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls + p->classes.size(), (int)p->classes_ana.size(),
+                            p->classes_ana.data(), v_fft, true, s));
   HIP_TRY(ensure_lds(std::max(p->lds_syn, p->lds_ana)));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
@@ -558,10 +640,12 @@ struct sht_batch_s {
   std::vector<sht_plan_t> plans;
   std::vector<int> variant;
   std::vector<WorkItem> inv[NUM_TILE_VARIANTS], dir[NUM_TILE_VARIANTS];
-  std::vector<FftItem> syn, ana;
+  std::vector<FftItem> syn, ana;  // tier-0 work groups first
+  int syn_split = 0, ana_split = 0;
   std::vector<size_t> ws_off;
   size_t ws_bytes = 0;
   size_t lds_syn = 0, lds_ana = 0;
+  size_t lds_syn_t[FFT_TIERS] = {}, lds_ana_t[FFT_TIERS] = {};
   std::vector<IoBind> io_host;
   bool bound = false;
   // device
@@ -573,7 +657,6 @@ struct sht_batch_s {
   FftItem* d_syn = nullptr;
   FftItem* d_ana = nullptr;
   int grid_inv[NUM_TILE_VARIANTS] = {}, grid_dir[NUM_TILE_VARIANTS] = {};
-  int grid_syn = 0, grid_ana = 0;
   hipGraphExec_t g_inv = nullptr, g_dir = nullptr;
 };
 
@@ -606,11 +689,10 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
     b->inv[v].clear();
     b->dir[v].clear();
   }
-  b->syn.clear();
-  b->ana.clear();
+  std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
   for (int i = 0; i < b->n; ++i) {
     legendre_items_raw(b->plans[i], b->variant[i], i, &b->inv[b->variant[i]], &b->dir[b->variant[i]]);
-    fft_items(b->plans[i], i, &b->syn, &b->ana);
+    fft_items(b->plans[i], i, st, at);
   }
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
     std::stable_sort(b->inv[v].begin(), b->inv[v].end(),
@@ -620,12 +702,14 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
     legendre_arrange(&b->inv[v]);
     legendre_arrange(&b->dir[v]);
   }
-  std::stable_sort(b->syn.begin(), b->syn.end(),
-                   [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
-  std::stable_sort(b->ana.begin(), b->ana.end(),
-                   [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
-  fft_arrange(b->plans.data(), &b->syn);
-  fft_arrange(b->plans.data(), &b->ana);
+  for (int t = 0; t < FFT_TIERS; ++t) {
+    std::stable_sort(st[t].begin(), st[t].end(),
+                     [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
+    std::stable_sort(at[t].begin(), at[t].end(),
+                     [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
+  }
+  b->syn_split = fft_join(b->plans.data(), false, st, &b->syn);
+  b->ana_split = fft_join(b->plans.data(), true, at, &b->ana);
 
   destroy_graphs(b);
   if (b->arena) {
@@ -680,11 +764,10 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
     if (persistent && ni) b->grid_inv[v] = std::min(ni, cus * legendre_blocks_per_cu(b->prec, v, true));
     if (persistent && nd) b->grid_dir[v] = std::min(nd, cus * legendre_blocks_per_cu(b->prec, v, false));
   }
-  // FFT launches keep one work group per item: measured on uneven batches,
-  // letting the hardware hand out work groups balanced the rings' very
-  // different lengths better than a resident grid looping over them.
-  b->grid_syn = (int)fft_grid_blocks((int)b->syn.size());
-  b->grid_ana = (int)fft_grid_blocks((int)b->ana.size());
+  // FFT launches keep one work group per item (fft_launch_tiers): measured
+  // on uneven batches, letting the hardware hand out work groups balanced the
+  // rings' very different lengths better than a resident grid looping over
+  // them.
   return SHT_OK;
 }
 
@@ -693,15 +776,15 @@ int batch_enqueue_inverse(sht_batch_s* b, hipStream_t s) {
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v)
     HIP_TRY(launch_legendre_inverse(b->d_plans, b->prec, v, b->d_inv[v], (int)b->inv[v].size(), b->d_io, none,
                                     b->grid_inv[v], s));
-  HIP_TRY(launch_fourier_synthesis(b->d_plans, b->prec, b->d_syn, (int)b->syn.size(), b->d_io, none, b->lds_syn,
-                                   b->grid_syn, s));
+  HIP_TRY(fft_launch_tiers(true, b->d_plans, b->prec, b->d_syn, (int)b->syn.size(), b->syn_split, b->d_io, none,
+                           b->lds_syn_t, s));
   return SHT_OK;
 }
 
 int batch_enqueue_direct(sht_batch_s* b, hipStream_t s) {
   const IoBind none{};
-  HIP_TRY(launch_fourier_analysis(b->d_plans, b->prec, b->d_ana, (int)b->ana.size(), b->d_io, none, b->lds_ana,
-                                  b->grid_ana, s));
+  HIP_TRY(fft_launch_tiers(false, b->d_plans, b->prec, b->d_ana, (int)b->ana.size(), b->ana_split, b->d_io, none,
+                           b->lds_ana_t, s));
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v)
     HIP_TRY(launch_legendre_direct(b->d_plans, b->prec, v, b->d_dir[v], (int)b->dir[v].size(), b->d_io, none,
                                    b->grid_dir[v], s));
@@ -784,6 +867,7 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->nfour = base->nfour;
   p->rings = base->rings;
   p->classes = base->classes;
+  p->classes_ana = base->classes_ana;
   p->ms = base->ms;
   p->ring_off = base->ring_off;
   p->four_row = base->four_row;
@@ -792,6 +876,10 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->fft_bytes = base->fft_bytes;
   p->lds_syn = base->lds_syn;
   p->lds_ana = base->lds_ana;
+  for (int t = 0; t < FFT_TIERS; ++t) {
+    p->lds_syn_t[t] = base->lds_syn_t[t];
+    p->lds_ana_t[t] = base->lds_ana_t[t];
+  }
   p->max_Lp = base->max_Lp;
   p->tables = base->tables;
   p->d_ms = base->d_ms;
@@ -803,9 +891,12 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->dp.Fp = p->Fp;
   p->variant = default_variant(p->prec, p->F);
   legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
-  fft_items(p, 0, &p->syn_items, &p->ana_items);
-  fft_arrange(&p, &p->syn_items);
-  fft_arrange(&p, &p->ana_items);
+  {
+    std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
+    fft_items(p, 0, st, at);
+    p->syn_split = fft_join(&p, false, st, &p->syn_items);
+    p->ana_split = fft_join(&p, true, at, &p->ana_items);
+  }
   int rc = build_own(p, (hipStream_t)hip_stream);
   if (rc == SHT_OK) {
     hipError_t e = hipStreamSynchronize((hipStream_t)hip_stream);
@@ -910,17 +1001,15 @@ int sht_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* strea
 
 int sht_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream) {
   if (!p || !four || !grid) return SHT_EINVAL;
-  HIP_TRY(launch_fourier_synthesis(p->d_self, p->prec, p->d_syn, (int)p->syn_items.size(), nullptr,
-                                   bind_of(nullptr, grid, four), p->lds_syn,
-                                   (int)fft_grid_blocks((int)p->syn_items.size()), (hipStream_t)stream));
+  HIP_TRY(fft_launch_tiers(true, p->d_self, p->prec, p->d_syn, (int)p->syn_items.size(), p->syn_split, nullptr,
+                           bind_of(nullptr, grid, four), p->lds_syn_t, (hipStream_t)stream));
   return SHT_OK;
 }
 
 int sht_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* stream) {
   if (!p || !four || !grid) return SHT_EINVAL;
-  HIP_TRY(launch_fourier_analysis(p->d_self, p->prec, p->d_ana, (int)p->ana_items.size(), nullptr,
-                                  bind_of(nullptr, grid, four), p->lds_ana,
-                                  (int)fft_grid_blocks((int)p->ana_items.size()), (hipStream_t)stream));
+  HIP_TRY(fft_launch_tiers(false, p->d_self, p->prec, p->d_ana, (int)p->ana_items.size(), p->ana_split, nullptr,
+                           bind_of(nullptr, grid, four), p->lds_ana_t, (hipStream_t)stream));
   return SHT_OK;
 }
 
@@ -965,6 +1054,10 @@ int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags
     off += align256(sht_workspace_size(plans[i]));
     b->lds_syn = std::max(b->lds_syn, plans[i]->lds_syn);
     b->lds_ana = std::max(b->lds_ana, plans[i]->lds_ana);
+    for (int t = 0; t < FFT_TIERS; ++t) {
+      b->lds_syn_t[t] = std::max(b->lds_syn_t[t], plans[i]->lds_syn_t[t]);
+      b->lds_ana_t[t] = std::max(b->lds_ana_t[t], plans[i]->lds_ana_t[t]);
+    }
   }
   b->ws_bytes = off;
   const int rc = batch_upload(b, (hipStream_t)stream);

@@ -431,7 +431,7 @@ size_t fft_grid_blocks(int nitems) { return (size_t)nitems; }
 // neighbouring lanes read neighbouring fields of one Fourier row.
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int fb, int fend,
                                                 const T* __restrict__ four, T* __restrict__ grid) {
   typedef typename V2T<T>::type C;
@@ -446,18 +446,18 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
   const bool blue = cl.bluestein;
   const int64_t Fp = p.Fp;
   const int gs = cl.gshift, G = 1 << gs;
-  const int nt = FFT_THREADS >> gs;
+  const int nt = NT >> gs;
   const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
   const uint32_t fs = lds_stride(L);
   {
     // Z_q and Z_{h-q} are built from the same two coefficients X_q and
     // X_{h-q}, so pair p = q (0 <= q <= h/2) loads them once and writes both
     const int np = (h / 2 + 1) << gs;
-    for (int e0 = threadIdx.x; e0 < np; e0 += FFT_SWEEP * FFT_THREADS) {
+    for (int e0 = threadIdx.x; e0 < np; e0 += FFT_SWEEP * NT) {
       C xa[FFT_SWEEP], xb[FFT_SWEEP], pa[FFT_SWEEP], pb[FFT_SWEEP], ca[FFT_SWEEP], cb[FFT_SWEEP];
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
-        const int e = e0 + u * FFT_THREADS;
+        const int e = e0 + u * NT;
         const int s = e & (G - 1), q = e >> gs, q2 = h - q;
         const bool ok = e < np && fb + s < fend;
         const bool two = ok && q >= 1 && q2 != q;  // q2 < h is a distinct index
@@ -471,7 +471,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
       }
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
-        const int e = e0 + u * FFT_THREADS;
+        const int e = e0 + u * NT;
         if (e < np) {
           const int s = e & (G - 1), q = e >> gs, q2 = h - q;
           C A = xa[u];
@@ -501,7 +501,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
     // chirp-z classes: zero padding h <= t < L
     if (blue) {
       const int nz = (L - h) << gs;
-      for (int e = threadIdx.x; e < nz; e += FFT_THREADS) {
+      for (int e = threadIdx.x; e < nz; e += NT) {
         const int s = e & (G - 1), t = h + (e >> gs);
         lds_store(lds_elem<C>(s * fs + t), C{0, 0});
       }
@@ -522,17 +522,18 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
 // The north result waits in LDS (G (mmax + 1) values after the transform
 // buffers) while the mirror ring is transformed; the output step writes
 // element e as (m = e / G, s = e mod G) so that neighbouring lanes write
-// neighbouring fields of one Fourier row.
+// neighbouring fields of one Fourier row.  (Parking it in its output row
+// instead measured slower: the read-back is another strided gather.)
 // ---------------------------------------------------------------------------
 
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int fb, int fend,
                                                const T* __restrict__ grid, T* __restrict__ four) {
   typedef typename V2T<T>::type C;
   const RingInfo rn = gload(p.rings + ring);
   const RingInfo rs = gload(p.rings + rn.mirror);
-  const FftClass cl = gload(p.classes + rn.cls);
-  const int32_t* rad = p.classes[rn.cls].rad;
+  const FftClass cl = gload(p.classes_ana + rn.cls);
+  const int32_t* rad = p.classes_ana[rn.cls].rad;
   const C* tabs = (const C*)p.fft;
   const int h = cl.h, mmax = rn.mmax, L = cl.L;
   const int gs = cl.gshift, G = 1 << gs;
@@ -543,7 +544,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   C* fc = (C*)four;
   const bool blue = cl.bluestein;
   const T scale = (T)(gload(p.w + ring) / (double)rn.nlon);
-  const int nt = FFT_THREADS >> gs;
+  const int nt = NT >> gs;
   const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
   const int Q = blue ? L : h;
   const int M = mmax + 1;
@@ -570,16 +571,16 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
       __syncthreads();
       dft_h<T, false>(dst, cl, rad, tabs, nullptr, lt, nt);
       const int nm = M << gs;
-      for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * FFT_THREADS) {
+      for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * NT) {
         C pm[FFT_SWEEP];
 #pragma unroll
         for (int u = 0; u < FFT_SWEEP; ++u) {
-          const int e = e0 + u * FFT_THREADS;
+          const int e = e0 + u * NT;
           pm[u] = e < nm ? gload(post + (e >> gs)) : C{0, 0};
         }
 #pragma unroll
         for (int u = 0; u < FFT_SWEEP; ++u) {
-          const int e = e0 + u * FFT_THREADS;
+          const int e = e0 + u * NT;
           if (e >= nm) continue;
           const int s = e & (G - 1), m = e >> gs;
           const C zm = lds_load(lds_elem<C>(s * fs + m));
@@ -611,83 +612,104 @@ size_t fft_lds_bytes(int prec, int L, int mmax, int G) {
   return c * lds_slots((size_t)G * (lds_stride(L) + (mmax >= 0 ? (size_t)mmax + 1 : 0)));
 }
 
-// Kernels: work groups loop over the items (grid stride).  FP32 kernels are
-// held to 128 VGPRs so that two 512-thread work groups share a CU (4 waves
-// per SIMD); FP64 ones need twice the registers and get 2 waves per SIMD.
+// Kernels: work groups loop over the items (grid stride), one kernel per
+// work-group size NT.  FP32 kernels are held to 128 VGPRs (4 waves per SIMD:
+// four 256-thread or two 512-thread work groups per CU); FP64 ones need twice
+// the registers and get 2 waves per SIMD.
 template <typename T>
 struct FftWaves {
   static constexpr int value = sizeof(T) == 4 ? 4 : 2;
 };
 
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS, FftWaves<T>::value) void fourier_synthesis_kernel(const DevPlan* __restrict__ plans,
-                                                                        const FftItem* __restrict__ items, int nitems,
-                                                                        const IoBind* __restrict__ io, IoBind io0) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_synthesis_kernel(const DevPlan* __restrict__ plans,
+                                                                                  const FftItem* __restrict__ items,
+                                                                                  int nitems,
+                                                                                  const IoBind* __restrict__ io,
+                                                                                  IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const FftItem it = gload(items + w);
     if (it.ring < 0) continue;
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    synthesis_group<T>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid);
+    synthesis_group<T, NT>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid);
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(FFT_THREADS, FftWaves<T>::value) void fourier_analysis_kernel(const DevPlan* __restrict__ plans,
-                                                                       const FftItem* __restrict__ items, int nitems,
-                                                                       const IoBind* __restrict__ io, IoBind io0) {
+template <typename T, int NT>
+__global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_analysis_kernel(const DevPlan* __restrict__ plans,
+                                                                                 const FftItem* __restrict__ items,
+                                                                                 int nitems,
+                                                                                 const IoBind* __restrict__ io,
+                                                                                 IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const FftItem it = gload(items + w);
     if (it.ring < 0) continue;
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    analysis_group<T>(p, it.ring, it.f0, it.fend, (const T*)b.grid, (T*)b.ws);
+    analysis_group<T, NT>(p, it.ring, it.f0, it.fend, (const T*)b.grid, (T*)b.ws);
   }
 }
 
-static hipError_t launch_fft(const void* f, int grid_blocks, size_t lds, hipStream_t s, const DevPlan* plans,
-                             const FftItem* items, int nitems, const IoBind* io, IoBind io0) {
+// The kernel of a precision, direction and tier.
+static const void* fft_kernel(int prec, bool synthesis, int tier) {
+  if (synthesis) {
+    if (prec == SHT_FP64)
+      return tier ? (const void*)fourier_synthesis_kernel<double, FFT_THREADS>
+                  : (const void*)fourier_synthesis_kernel<double, FFT_THREADS_SMALL>;
+    return tier ? (const void*)fourier_synthesis_kernel<float, FFT_THREADS>
+                : (const void*)fourier_synthesis_kernel<float, FFT_THREADS_SMALL>;
+  }
+  if (prec == SHT_FP64)
+    return tier ? (const void*)fourier_analysis_kernel<double, FFT_THREADS>
+                : (const void*)fourier_analysis_kernel<double, FFT_THREADS_SMALL>;
+  return tier ? (const void*)fourier_analysis_kernel<float, FFT_THREADS>
+              : (const void*)fourier_analysis_kernel<float, FFT_THREADS_SMALL>;
+}
+
+static hipError_t launch_fft(const void* f, int threads, int grid_blocks, size_t lds, hipStream_t s,
+                             const DevPlan* plans, const FftItem* items, int nitems, const IoBind* io, IoBind io0) {
   void* args[] = {(void*)&plans, (void*)&items, (void*)&nitems, (void*)&io, (void*)&io0};
-  return hipLaunchKernel(f, dim3(grid_blocks), dim3(FFT_THREADS), args, lds, s);
+  return hipLaunchKernel(f, dim3(grid_blocks), dim3(threads), args, lds, s);
 }
 
-hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, int tier, const FftItem* items, int nitems,
                                     const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  const void* f = prec == SHT_FP64 ? (const void*)fourier_synthesis_kernel<double>
-                                   : (const void*)fourier_synthesis_kernel<float>;
-  return launch_fft(f, grid_blocks, lds, s, plans, items, nitems, io, io0);
+  return launch_fft(fft_kernel(prec, true, tier), fft_tier_threads(tier), grid_blocks, lds, s, plans, items, nitems,
+                    io, io0);
 }
 
-hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, int tier, const FftItem* items, int nitems,
                                    const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
-  const void* f = prec == SHT_FP64 ? (const void*)fourier_analysis_kernel<double>
-                                   : (const void*)fourier_analysis_kernel<float>;
-  return launch_fft(f, grid_blocks, lds, s, plans, items, nitems, io, io0);
+  return launch_fft(fft_kernel(prec, false, tier), fft_tier_threads(tier), grid_blocks, lds, s, plans, items, nitems,
+                    io, io0);
 }
 
-int fft_blocks_per_cu(int prec, size_t lds) {
+int fft_blocks_per_cu(int prec, int tier, size_t lds) {
   int n = 0;
-  const void* f = prec == SHT_FP64 ? (const void*)fourier_synthesis_kernel<double>
-                                   : (const void*)fourier_synthesis_kernel<float>;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, FFT_THREADS, lds) != hipSuccess || n < 1) n = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fft_kernel(prec, true, tier), fft_tier_threads(tier), lds) !=
+          hipSuccess ||
+      n < 1)
+    n = 1;
   return n;
 }
 
 // Every FFT kernel addresses its dynamic LDS buffer from LDS address 0,
 // which holds only while the kernels declare no LDS of their own.
 hipError_t fft_set_max_lds(size_t bytes) {
-  const void* kernels[] = {(const void*)fourier_synthesis_kernel<double>, (const void*)fourier_synthesis_kernel<float>,
-                           (const void*)fourier_analysis_kernel<double>, (const void*)fourier_analysis_kernel<float>};
-  for (const void* f : kernels) {
-    hipFuncAttributes a;
-    hipError_t e = hipFuncGetAttributes(&a, f);
-    if (e != hipSuccess) return e;
-    if (a.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
-    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-  }
+  for (int prec : {SHT_FP64, SHT_FP32})
+    for (int syn = 0; syn < 2; ++syn)
+      for (int tier = 0; tier < FFT_TIERS; ++tier) {
+        const void* f = fft_kernel(prec, syn != 0, tier);
+        hipFuncAttributes a;
+        hipError_t e = hipFuncGetAttributes(&a, f);
+        if (e != hipSuccess) return e;
+        if (a.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
+        e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+      }
   return hipSuccess;
 }
 

@@ -27,8 +27,15 @@ constexpr int FPAD = 16;
 
 // FFT: threads per work group and complex values each thread may hold in
 // registers during one pass; together they bound the transform length.
-// A work group takes FFT_FCHUNK fields of one ring, G of them at a time.
+// Transforms run in work groups of FFT_THREADS_SMALL threads (tier 0) where
+// that many threads per field cover every pass with the fewest passes, else
+// of FFT_THREADS (tier 1): smaller groups wait at smaller barriers and more
+// of them share a CU.  A work group transforms up to G fields of one ring
+// side by side; work is listed in chunks of FFT_FCHUNK fields.
 constexpr int FFT_THREADS = 512;
+constexpr int FFT_THREADS_SMALL = 256;
+constexpr int FFT_TIERS = 2;
+__host__ __device__ constexpr int fft_tier_threads(int tier) { return tier ? FFT_THREADS : FFT_THREADS_SMALL; }
 constexpr int FFT_REGS = 20;
 constexpr int FFT_MAX_RADICES = 20;
 constexpr int FFT_FCHUNK = 16;
@@ -123,8 +130,9 @@ struct FftClass {
   int32_t bluestein;
   int32_t nrad;
   int32_t rad[FFT_MAX_RADICES];
-  int32_t G;          // fields transformed side by side per round (power of two)
-  int32_t gshift;     // log2 G; each field gets FFT_THREADS / G threads
+  int32_t G;          // fields transformed side by side per work group (power of two)
+  int32_t gshift;     // log2 G; each field gets fft_tier_threads(tier) / G threads
+  int32_t tier;       // work-group size: fft_tier_threads(tier)
   int64_t root_off;   // L - 1 twiddles, pass after pass: exp(-2 pi i r k / (Ns R)) at
                       // k (R - 1) + r - 1 of the pass table (k < Ns, 1 <= r < R)
   int64_t post_off;   // h complex values exp(-2 pi i q / (2h))
@@ -182,7 +190,8 @@ struct DevPlan {
   int32_t N, nlat, nh, F, Fp;
   int64_t npts, nspec;
   const RingInfo* rings;
-  const FftClass* classes;
+  const FftClass* classes;      // synthesis work groups
+  const FftClass* classes_ana;  // analysis work groups (same lengths and tables)
   const MInfo* ms;
   const double* mu;
   const double* w;
@@ -199,8 +208,9 @@ struct DevPlan {
 hipError_t launch_gauss(int nlat, double* mu, double* w, hipStream_t s);
 hipError_t launch_pbar_planes(const DevPlan& p, int prec, const MInfo* d_ms, int nm, int max_Lp,
                               void* tab, int64_t plane_elems, hipStream_t s);
+// all of each class's tables, or (twiddles_only) only its twiddles
 hipError_t launch_fft_tables(const DevPlan& p, int prec, const FftClass* d_cls, int ncls,
-                             const FftClass* h_cls, void* fft, hipStream_t s);
+                             const FftClass* h_cls, void* fft, bool twiddles_only, hipStream_t s);
 hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& mi, int64_t plane,
                                       double* out, hipStream_t s);
 
@@ -217,15 +227,17 @@ bool legendre_variant_supported(int prec, int variant);
 // work groups per CU the kernel of a variant can keep resident
 int legendre_blocks_per_cu(int prec, int variant, bool inverse);
 
-// fft.hip.  Same launch model; `nvirt` virtual work groups (fft_grid_blocks)
-// are spread over `grid_blocks` real ones.
-hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+// fft.hip.  Same launch model, one launch per tier: the items of one launch
+// all belong to classes of that tier.
+hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, int tier, const FftItem* items, int nitems,
                                     const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s);
-hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, const FftItem* items, int nitems,
+hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, int tier, const FftItem* items, int nitems,
                                    const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s);
 hipError_t fft_set_max_lds(size_t bytes);
+// LDS of a work group of G transforms of length L; mmax >= 0 adds the
+// analysis' north results (mmax + 1 per field)
 size_t fft_lds_bytes(int prec, int L, int mmax, int G);
 size_t fft_grid_blocks(int nitems);
-int fft_blocks_per_cu(int prec, size_t lds);
+int fft_blocks_per_cu(int prec, int tier, size_t lds);
 
 }  // namespace shtmi
