@@ -22,7 +22,7 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/legendre.hip", "csrc/fft.hip", "csrc/sht_internal.h"]
+SOURCES = ["csrc/legendre.hip", "csrc/fft.hip", "csrc/sht_internal.h", "csrc/capi.hip"]
 STAGE_KERNELS = {
     "legendre_inverse": "legendre_inverse",
     "fourier_synthesis": "fourier_synthesis_kernel",
@@ -94,16 +94,19 @@ def traffic_json(fetch_csv, write_csv, copy_bytes, out_json, commands):
     # KiB reading -> bytes: the copy moved copy_bytes in and copy_bytes out
     scale_f = copy_bytes / cf
     scale_w = copy_bytes / cw
+    # A stage may be several kernels, each dispatched once per stage (the FFT
+    # stages run one launch per work-group size): its bytes are the sum of
+    # their per-dispatch averages.
     kernels = {}
     for stage, key in STAGE_KERNELS.items():
-        fk = [k for k in fetch if key in k and "shtmi" in k]
-        wk = [k for k in write if key in k and "shtmi" in k]
+        fk = sorted(k for k in fetch if key in k and "shtmi" in k)
+        wk = sorted(k for k in write if key in k and "shtmi" in k)
         if not fk or not wk:
             continue
-        f = sum(fetch[fk[0]]) / len(fetch[fk[0]])
-        w = sum(write[wk[0]]) / len(write[wk[0]])
-        kernels[stage] = {"kernel": _short(fk[0]), "fetch_bytes": f * scale_f, "write_bytes": w * scale_w,
-                          "fetch_kib_raw": f, "write_kib_raw": w}
+        f = sum(sum(fetch[k]) / len(fetch[k]) for k in fk)
+        w = sum(sum(write[k]) / len(write[k]) for k in wk)
+        kernels[stage] = {"kernel": " + ".join(_short(k) for k in fk), "fetch_bytes": f * scale_f,
+                          "write_bytes": w * scale_w, "fetch_kib_raw": f, "write_kib_raw": w}
     out = {
         "source_sha256": source_hash(),
         "copy_bytes": copy_bytes,
@@ -120,8 +123,9 @@ def traffic_json(fetch_csv, write_csv, copy_bytes, out_json, commands):
 
 
 def measured_traffic(path, stage):
-    """HBM bytes per dispatch of ``stage`` from a committed traffic file, or
-    None when the file is absent or the kernel sources changed since."""
+    """HBM bytes per call of ``stage`` (all its kernels) from a committed
+    traffic file, or None when the file is absent or the kernel sources
+    changed since."""
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
