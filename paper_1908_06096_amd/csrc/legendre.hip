@@ -691,11 +691,14 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   const int64_t rowlen = 2 * (int64_t)p.Fp;
   const int nj = (mi.L + KJ - 1) / KJ;
 
-  // X unit: (parity, column quad, ring octet).  Rings past L are read at
-  // ring L - 1 (their table rows are zero or past the table), and columns
-  // past the row end (outputs never stored) are clamped into the row.
-  const int x_oct = tid % (KJ / 8);
-  const int x_cq = (tid / (KJ / 8)) % (BC / 4);
+  // X unit: (parity, ring octet, column quad), the column quad fastest so
+  // that a load instruction covers two rings' 512-byte row segments (with
+  // the ring octet fastest it covered four rings' 256-byte segments, and
+  // the L1's tag lookups made the gather cost 30% more).  Rings past L are
+  // read at ring L - 1 (their table rows are zero or past the table), and
+  // columns past the row end (outputs never stored) are clamped into the row.
+  const int x_cq = tid % (BC / 4);
+  const int x_oct = (tid / (BC / 4)) % (KJ / 8);
   const int x_par = tid / ((KJ / 8) * (BC / 4));
   const int x_c = min(it.c0 + 4 * x_cq, 2 * p.Fp - 4);
   // table unit: (plane, parity, chunk, ring octet), read through one buffer
