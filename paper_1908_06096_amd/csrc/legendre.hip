@@ -473,6 +473,12 @@ constexpr int BPAD = 8;
 // field index, zeros selected) and split into the one spectral stage.
 constexpr int BF_BM = 128, BF_BN = 64, BF_KI = 32;
 
+// Spectral-stage slot of column c in k chunk ch: the column XOR the chunk,
+// which stays within c's aligned group of 16 columns (so 16 lanes reading
+// 16 consecutive columns of one chunk still cover all banks) and spreads
+// the chunks of one column over different banks.
+__device__ __forceinline__ int bsw(int c, int ch) { return c ^ ch; }
+
 __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const WorkItem it, const float* __restrict__ spec,
                                                     float* __restrict__ four) {
   constexpr int BM = BF_BM, BN = BF_BN, KI = BF_KI;
@@ -525,10 +531,13 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
       }
     }
   };
-  // spectral values: lane fi = tid & 31 is the field, sg = tid >> 5 the
-  // segment of 8 consecutive n - m (both parities) within the step
-  // (the descriptor starts at the tile's first field, so offsets stay small)
-  const int fi = tid & 31, sg = tid >> 5;
+  // spectral values: thread (fi, sg) loads segment sg (8 consecutive n - m,
+  // both parities: 64 contiguous bytes) of field fi within the step.  The
+  // segment is the fastest index, so one load instruction touches 8 fields'
+  // rows rather than 32 (the L1's tag lookups, not the bytes, bounded the
+  // gather).  The descriptor starts at the tile's first field, so offsets
+  // stay small.
+  const int fi = tid >> 3, sg = tid & 7;
   const int f0 = it.c0 / 2;
   const int f = f0 + fi;
   const uint32_t fl = (uint32_t)((f < p.F ? f : p.F - 1) - f0);
@@ -575,7 +584,9 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
           const float2 u = rb[4 * e + pa], w = rb[4 * e + 2 + pa];
           split2_bf16(comp ? u.y : u.x, comp ? w.y : w.x, &h[e], &l[e]);
         }
-        const int slot = ((pa * 2) * NCK + (sg >> 1)) * BN + 2 * fi + comp;
+        // column swizzled by the chunk (see bsw): the 8 lanes of a field
+        // write 4 chunks 1 KB apart, which would share banks
+        const int slot = ((pa * 2) * NCK + (sg >> 1)) * BN + bsw(2 * fi + comp, sg >> 1);
         uint2* dh = (uint2*)(Bs + slot) + (sg & 1);
         uint2* dl = (uint2*)(Bs + slot + NCK * BN) + (sg & 1);
         *dh = make_uint2(h[0], h[1]);
@@ -594,7 +605,7 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
     uint4 bh[4], bl[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int c = 16 * j + (lane & 15);
+      const int c = bsw(16 * j + (lane & 15), lane >> 4);
       bh[j] = Bs[((par * 2 + 0) * NCK + (lane >> 4)) * BN + c];
       bl[j] = Bs[((par * 2 + 1) * NCK + (lane >> 4)) * BN + c];
     }
