@@ -178,13 +178,10 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
 #pragma unroll
       for (int v = 0; v < KCH / VN; ++v) ra[a][v] = rsrc_load<V>(a_par[a] ? t_rs1 : t_rs0, a_off[a] + v * sizeof(V), sa);
     }
+    // raw loads only: anything computed from them here would wait for them
     const uint32_t sb = (uint32_t)kc * (2 * KI) * (uint32_t)sizeof(C2);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      C2 x = rsrc_load<C2>(b_rs, b_off + TPF * j * (uint32_t)sizeof(C2), sb);
-      if (m0) x.y = 0;
-      rb[j] = x;
-    }
+    for (int j = 0; j < NB; ++j) rb[j] = rsrc_load<C2>(b_rs, b_off + TPF * j * (uint32_t)sizeof(C2), sb);
   };
 
   acc_t acc[2][IM][IN];
@@ -207,6 +204,10 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
     for (int j = 0; j < NB; ++j) {
       const int k = (q >> 1) + (TPF / 2) * j;
       *(C2*)&Bs[b_par][k][2 * fi] = rb[j];
+      // Im a_n^0 is dropped: a constant store, so that nothing is computed
+      // from the prefetched registers before this step (the compiler would
+      // compute it right after the loads and wait for them there)
+      if (m0) Bs[b_par][k][2 * fi + 1] = 0;
     }
     __syncthreads();
     if (kc + 1 < nk) fetch(kc + 1);
