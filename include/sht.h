@@ -61,10 +61,10 @@
  *
  *   Fourier workspace, analysis form (written by sht_fourier_analysis,
  *   read by sht_legendre_direct): for north ring j (0..nlat/2-1), m and
- *   parity p (0: symmetric S, 1: antisymmetric A) the complex value is at
- *   ((four_row[j] + m) * 2 + p) * fpad + f, where
- *   S = (w_j/nlon_j) (chat(ring j) + chat(mirror ring)) and
- *   A = (w_j/nlon_j) (chat(ring j) - chat(mirror ring)).
+ *   slot p the complex value is at ((four_row[j] + m) * 2 + p) * fpad + f:
+ *   slot 0 holds (w_j/nlon_j) chat(ring j), slot 1 (w_j/nlon_j)
+ *   chat(mirror ring).  sht_legendre_direct forms the symmetric and
+ *   antisymmetric parts S = slot 0 + slot 1 and A = slot 0 - slot 1.
  *
  * Ownership and concurrency: a plan owns its device tables and metadata and
  * is immutable after creation.  sht_inverse / sht_direct and the stage calls
@@ -198,14 +198,14 @@ int sht_legendre_inverse(sht_plan_t plan, const void* spec, void* fourier,
 int sht_fourier_synthesis(sht_plan_t plan, const void* fourier, void* grid,
                           void* hip_stream);
 
-/* Stage 1 of analysis: per ring pair, the real DFT, the (w_j / nlon_j)
- * scaling and the symmetric/antisymmetric fold, written in the analysis
- * form of the Fourier workspace. */
+/* Stage 1 of analysis: per ring, the real DFT and the (w_j / nlon_j)
+ * scaling, written in the analysis form of the Fourier workspace. */
 int sht_fourier_analysis(sht_plan_t plan, const void* grid, void* fourier,
                          void* hip_stream);
 
 /* Stage 2 of analysis: per m, a_n^m = Pbar^T S (n - m even) or Pbar^T A
- * (n - m odd) summed over the north rings carrying m. */
+ * (n - m odd) summed over the north rings carrying m, with S and A formed
+ * from the two slots of the analysis form. */
 int sht_legendre_direct(sht_plan_t plan, const void* fourier, void* spec,
                         void* hip_stream);
 

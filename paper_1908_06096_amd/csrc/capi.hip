@@ -157,8 +157,7 @@ struct sht_plan_s {
   int elem = 8;
   int variant = TILE_C128;
   std::vector<RingInfo> rings;
-  std::vector<FftClass> classes;      // synthesis work groups
-  std::vector<FftClass> classes_ana;  // analysis work groups (same lengths and tables)
+  std::vector<FftClass> classes;
   std::vector<MInfo> ms;
   std::vector<int64_t> ring_off, four_row;
   std::vector<WorkItem> inv_items, dir_items;
@@ -250,9 +249,9 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
   for (int j : order)
     for (int f0 = 0; f0 < p->F; f0 += FFT_FCHUNK) {
       const int fend = std::min(f0 + FFT_FCHUNK, p->F);
-      const int cls = p->rings[j].cls;
-      syn[p->classes[cls].tier].push_back(FftItem{j, f0, plan, fend});
-      if (j < p->nh) ana[p->classes_ana[cls].tier].push_back(FftItem{j, f0, plan, fend});
+      const int t = p->classes[p->rings[j].cls].tier;
+      syn[t].push_back(FftItem{j, f0, plan, fend});
+      if (j < p->nh) ana[t].push_back(FftItem{j, f0, plan, fend});
     }
 }
 
@@ -264,7 +263,7 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
 // of its eight): they run on one XCD at the same time, and their strided
 // reads and writes of the chunk's Fourier rows (fields are the innermost
 // index) meet in that XCD's L2.
-void fft_arrange(const sht_plan_t* plans, bool analysis, std::vector<FftItem>* items) {
+void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
   std::vector<FftItem> chunks;
   chunks.swap(*items);
   for (size_t c0 = 0; c0 < chunks.size(); c0 += NUM_XCD) {
@@ -273,7 +272,7 @@ void fft_arrange(const sht_plan_t* plans, bool analysis, std::vector<FftItem>* i
     for (int k = 0; k < nc; ++k) {
       const FftItem& c = chunks[c0 + k];
       const sht_plan_s* p = plans[c.plan];
-      G[k] = (analysis ? p->classes_ana : p->classes)[p->rings[c.ring].cls].G;
+      G[k] = p->classes[p->rings[c.ring].cls].G;
       ng[k] = (c.fend - c.f0 + G[k] - 1) / G[k];
       most = std::max(most, ng[k]);
     }
@@ -290,21 +289,17 @@ void fft_arrange(const sht_plan_t* plans, bool analysis, std::vector<FftItem>* i
   }
 }
 
-// Work-group size and fields per work group of each FFT class for one
-// direction (the analysis also keeps the north ring's mmax + 1 results per
-// field in LDS).  Tier 0 (FFT_THREADS_SMALL threads) where that many threads
+// Work-group size and fields per work group of each FFT class.  Tier 0 (FFT_THREADS_SMALL threads) where that many threads
 // per field reach the pass count FFT_THREADS threads do, and one field's LDS
 // leaves the small groups' occupancy at what their registers allow (a
 // launch's LDS per group is its largest item's).  G: the most fields (up to
 // FFT_MAX_G) whose threads per field (the tier's work-group size / G) still
 // hold every pass with the same pass count and whose LDS fits the tier's
 // budget, the most LDS that keeps the occupancy the tier's longest class has
-// with G = 1.  A ring of class h carries mmax = min(N, h - 1).  The classes
-// come in with the radices for FFT_THREADS threads per field.
-void choose_groups(int prec, int N, bool analysis, std::vector<FftClass>* cls) {
-  auto lds = [&](const FftClass& c, int G) {
-    return fft_lds_bytes(prec, c.L, analysis ? std::min(N, c.h - 1) : -1, G);
-  };
+// with G = 1.  The classes come in with the radices for FFT_THREADS threads
+// per field.
+void choose_groups(int prec, std::vector<FftClass>* cls) {
+  auto lds = [&](const FftClass& c, int G) { return fft_lds_bytes(prec, c.L, G); };
   const int full = fft_blocks_per_cu(prec, 0, 0);
   for (FftClass& c : *cls) {
     const std::vector<int> rs = radices(c.L, FFT_THREADS_SMALL);
@@ -362,9 +357,9 @@ hipError_t fft_launch_tiers(bool synthesis, const DevPlan* plans, int prec, cons
 // One launch list from per-tier chunk lists (each in launch order): each
 // tier's chunks become its work groups, tier 0 first.  Returns the number of
 // tier-0 work groups.
-int fft_join(const sht_plan_t* plans, bool analysis, std::vector<FftItem>* tiers, std::vector<FftItem>* out) {
+int fft_join(const sht_plan_t* plans, std::vector<FftItem>* tiers, std::vector<FftItem>* out) {
   out->clear();
-  for (int t = 0; t < FFT_TIERS; ++t) fft_arrange(plans, analysis, &tiers[t]);
+  for (int t = 0; t < FFT_TIERS; ++t) fft_arrange(plans, &tiers[t]);
   out->insert(out->end(), tiers[0].begin(), tiers[0].end());
   const int split = (int)out->size();
   for (int t = 1; t < FFT_TIERS; ++t) out->insert(out->end(), tiers[t].begin(), tiers[t].end());
@@ -436,30 +431,16 @@ int build_host(sht_plan_s* p) {
     }
     p->classes.push_back(c);
   }
-  // Work groups of each direction (the analysis keeps more in LDS).  The
-  // twiddle table follows the radix sequence, so an analysis class whose
-  // radices differ from the synthesis' gets a twiddle table of its own.
-  p->classes_ana = p->classes;
-  choose_groups(p->prec, N, false, &p->classes);
-  choose_groups(p->prec, N, true, &p->classes_ana);
-  for (size_t i = 0; i < p->classes.size(); ++i) {
-    const FftClass& c = p->classes[i];
-    FftClass& a = p->classes_ana[i];
-    if (a.nrad != c.nrad || !std::equal(a.rad, a.rad + a.nrad, c.rad)) {
-      a.root_off = off;
-      off += a.L;
-    }
-  }
   p->fft_bytes = (size_t)off * csize;
+  choose_groups(p->prec, &p->classes);
   for (auto& r : p->rings) {
     const int h = r.nlon / 2;
     r.cls = (int)(std::lower_bound(hs.begin(), hs.end(), h) - hs.begin());
-    const FftClass& cs = p->classes[r.cls];
-    const FftClass& ca = p->classes_ana[r.cls];
-    size_t& ls = p->lds_syn_t[cs.tier];
-    size_t& la = p->lds_ana_t[ca.tier];
-    ls = std::max(ls, fft_lds_bytes(p->prec, cs.L, -1, cs.G));
-    la = std::max(la, fft_lds_bytes(p->prec, ca.L, r.mmax, ca.G));
+    const FftClass& c = p->classes[r.cls];
+    size_t& ls = p->lds_syn_t[c.tier];
+    size_t& la = p->lds_ana_t[c.tier];
+    ls = std::max(ls, fft_lds_bytes(p->prec, c.L, c.G));
+    la = std::max(la, fft_lds_bytes(p->prec, c.L, c.G));
     p->lds_syn = std::max(p->lds_syn, ls);
     p->lds_ana = std::max(p->lds_ana, la);
   }
@@ -502,8 +483,8 @@ int build_host(sht_plan_s* p) {
   {
     std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
     fft_items(p, 0, st, at);
-    p->syn_split = fft_join(&p, false, st, &p->syn_items);
-    p->ana_split = fft_join(&p, true, at, &p->ana_items);
+    p->syn_split = fft_join(&p, st, &p->syn_items);
+    p->ana_split = fft_join(&p, at, &p->ana_items);
   }
   return SHT_OK;
 }
@@ -565,7 +546,7 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   };
   const Part parts[] = {
       {&v_rings, sizeof(RingInfo) * p->rings.size()},
-      {&v_cls, 2 * sizeof(FftClass) * p->classes.size()},  // synthesis, then analysis classes
+      {&v_cls, sizeof(FftClass) * p->classes.size()},
       {&v_ms, sizeof(MInfo) * p->ms.size()},
       {&v_mu, sizeof(double) * p->nlat},
       {&v_w, sizeof(double) * p->nlat},
@@ -596,7 +577,6 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   d.nspec = p->nspec;
   d.rings = (const RingInfo*)v_rings;
   d.classes = (const FftClass*)v_cls;
-  d.classes_ana = (const FftClass*)v_cls + p->classes.size();
   d.ms = (const MInfo*)v_ms;
   d.mu = (const double*)v_mu;
   d.w = (const double*)v_w;
@@ -607,18 +587,14 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   p->d_cls = (FftClass*)v_cls;
 
   HIP_TRY(hipMemcpyAsync(v_rings, p->rings.data(), parts[0].bytes, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), sizeof(FftClass) * p->classes.size(), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync((FftClass*)v_cls + p->classes.size(), p->classes_ana.data(),
-                         sizeof(FftClass) * p->classes_ana.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), parts[1].bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(v_ms, p->ms.data(), parts[2].bytes, hipMemcpyHostToDevice, s));
   int rc = build_own(p, s);
   if (rc != SHT_OK) return rc;
 
   HIP_TRY(launch_gauss(p->nlat, (double*)v_mu, (double*)v_w, s));
   HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane, s));
-  HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls, (int)p->classes.size(), p->classes.data(), v_fft, false, s));
-  HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls + p->classes.size(), (int)p->classes_ana.size(),
-                            p->classes_ana.data(), v_fft, true, s));
+  HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls, (int)p->classes.size(), p->classes.data(), v_fft, s));
   HIP_TRY(ensure_lds(std::max(p->lds_syn, p->lds_ana)));
   HIP_TRY(hipStreamSynchronize(s));
   HIP_TRY(hipGetLastError());
@@ -708,8 +684,8 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
     std::stable_sort(at[t].begin(), at[t].end(),
                      [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
   }
-  b->syn_split = fft_join(b->plans.data(), false, st, &b->syn);
-  b->ana_split = fft_join(b->plans.data(), true, at, &b->ana);
+  b->syn_split = fft_join(b->plans.data(), st, &b->syn);
+  b->ana_split = fft_join(b->plans.data(), at, &b->ana);
 
   destroy_graphs(b);
   if (b->arena) {
@@ -867,7 +843,6 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->nfour = base->nfour;
   p->rings = base->rings;
   p->classes = base->classes;
-  p->classes_ana = base->classes_ana;
   p->ms = base->ms;
   p->ring_off = base->ring_off;
   p->four_row = base->four_row;
@@ -894,8 +869,8 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   {
     std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
     fft_items(p, 0, st, at);
-    p->syn_split = fft_join(&p, false, st, &p->syn_items);
-    p->ana_split = fft_join(&p, true, at, &p->ana_items);
+    p->syn_split = fft_join(&p, st, &p->syn_items);
+    p->ana_split = fft_join(&p, at, &p->ana_items);
   }
   int rc = build_own(p, (hipStream_t)hip_stream);
   if (rc == SHT_OK) {

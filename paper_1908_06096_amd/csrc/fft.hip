@@ -516,14 +516,16 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
 }
 
 // ---------------------------------------------------------------------------
-// Analysis: north ring j and its mirror, the fields [f0, fend) side by side.
+// Analysis: north ring j and its mirror, one after the other, the fields
+// [f0, fend) side by side.
 //   Z = DFT_h(z),  X_m = (Z_m + conj Z_{h-m})/2 - (i/2) w^{-m} (Z_m - conj Z_{h-m}),
-//   chat_m = X_m / n;  S = w_j (chat_N + chat_S),  A = w_j (chat_N - chat_S).
-// The north result waits in LDS (G (mmax + 1) values after the transform
-// buffers) while the mirror ring is transformed; the output step writes
-// element e as (m = e / G, s = e mod G) so that neighbouring lanes write
-// neighbouring fields of one Fourier row.  (Parking it in its output row
-// instead measured slower: the read-back is another strided gather.)
+//   chat_m = X_m / n, written as w_j chat_m to the north ring's Fourier
+//   row: slot 0 for the ring, slot 1 for its mirror (the Legendre analysis
+//   forms S = N + S' and A = N - S' as it stages them, so neither ring
+//   waits in LDS for the other; one work item still takes both, which
+//   measured faster than one ring per item).  The output step writes
+//   element e as (m = e / G, s = e mod G) so that neighbouring lanes write
+//   neighbouring fields of one Fourier row.
 // ---------------------------------------------------------------------------
 
 template <typename T, int NT>
@@ -532,13 +534,12 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   typedef typename V2T<T>::type C;
   const RingInfo rn = gload(p.rings + ring);
   const RingInfo rs = gload(p.rings + rn.mirror);
-  const FftClass cl = gload(p.classes_ana + rn.cls);
-  const int32_t* rad = p.classes_ana[rn.cls].rad;
+  const FftClass cl = gload(p.classes + rn.cls);
+  const int32_t* rad = p.classes[rn.cls].rad;
   const C* tabs = (const C*)p.fft;
   const int h = cl.h, mmax = rn.mmax, L = cl.L;
   const int gs = cl.gshift, G = 1 << gs;
   const uint32_t fs = lds_stride(L);
-  const uint32_t keep = G * fs;  // first element of the north results
   const C* post = tabs + cl.post_off;
   const C* chirp = tabs + cl.chirp_off;
   C* fc = (C*)four;
@@ -548,68 +549,60 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
   const int Q = blue ? L : h;
   const int M = mmax + 1;
-  {
-    const int f = fb + sub;
-    for (int side = 0; side < 2; ++side) {
-      const uint32_t dst = sub * fs;
-      const C* g = (const C*)(grid + (int64_t)min(f, fend - 1) * p.npts + (side ? rs.goff : rn.goff));
-      for (int t0 = lt; t0 < Q; t0 += FFT_SWEEP * nt) {
-        C z[FFT_SWEEP], c[FFT_SWEEP];
+  const int f = fb + sub;
+  const uint32_t dst = sub * fs;
+  for (int side = 0; side < 2; ++side) {
+    const C* g = (const C*)(grid + (int64_t)min(f, fend - 1) * p.npts + (side ? rs.goff : rn.goff));
+    for (int t0 = lt; t0 < Q; t0 += FFT_SWEEP * nt) {
+      C z[FFT_SWEEP], c[FFT_SWEEP];
 #pragma unroll
-        for (int u = 0; u < FFT_SWEEP; ++u) {
-          const int t = t0 + u * nt;
-          const bool ok = t < h && f < fend;
-          z[u] = ok ? gload(g + t) : C{0, 0};
-          c[u] = (ok && blue) ? gload(chirp + t) : C{1, 0};
-        }
-#pragma unroll
-        for (int u = 0; u < FFT_SWEEP; ++u) {
-          const int t = t0 + u * nt;
-          if (t < Q) lds_store(lds_elem<C>(dst + t), blue ? cmul(z[u], c[u]) : z[u]);
-        }
+      for (int u = 0; u < FFT_SWEEP; ++u) {
+        const int t = t0 + u * nt;
+        const bool ok = t < h && f < fend;
+        z[u] = ok ? gload(g + t) : C{0, 0};
+        c[u] = (ok && blue) ? gload(chirp + t) : C{1, 0};
       }
-      __syncthreads();
-      dft_h<T, false>(dst, cl, rad, tabs, nullptr, lt, nt);
-      const int nm = M << gs;
-      for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * NT) {
-        C pm[FFT_SWEEP];
 #pragma unroll
-        for (int u = 0; u < FFT_SWEEP; ++u) {
-          const int e = e0 + u * NT;
-          pm[u] = e < nm ? gload(post + (e >> gs)) : C{0, 0};
-        }
-#pragma unroll
-        for (int u = 0; u < FFT_SWEEP; ++u) {
-          const int e = e0 + u * NT;
-          if (e >= nm) continue;
-          const int s = e & (G - 1), m = e >> gs;
-          const C zm = lds_load(lds_elem<C>(s * fs + m));
-          const C zr = cconj(lds_load(lds_elem<C>(s * fs + (m == 0 ? 0 : h - m))));
-          const C sm = cadd(zm, zr);
-          const C d = csub(zm, zr);
-          const C t = cmul(pm[u], d);
-          // X = sm/2 - (i/2) t
-          C x = C{(T)0.5 * (sm.x + t.y), (T)0.5 * (sm.y - t.x)};
-          if (m == 0) x = C{zm.x + zm.y, 0};
-          x = cscale(x, scale);
-          if (side == 0) {
-            lds_store(lds_elem<C>(keep + s * M + m), x);
-          } else if (fb + s < fend) {
-            const C xn = lds_load(lds_elem<C>(keep + s * M + m));
-            C* row = fc + ((rn.frow + m) * 2) * (int64_t)p.Fp + fb + s;
-            gstore(row, cadd(xn, x));
-            gstore(row + p.Fp, csub(xn, x));
-          }
-        }
+      for (int u = 0; u < FFT_SWEEP; ++u) {
+        const int t = t0 + u * nt;
+        if (t < Q) lds_store(lds_elem<C>(dst + t), blue ? cmul(z[u], c[u]) : z[u]);
       }
-      __syncthreads();
     }
+    __syncthreads();
+    dft_h<T, false>(dst, cl, rad, tabs, nullptr, lt, nt);
+    const int nm = M << gs;
+    for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * NT) {
+      C pm[FFT_SWEEP];
+#pragma unroll
+      for (int u = 0; u < FFT_SWEEP; ++u) {
+        const int e = e0 + u * NT;
+        pm[u] = e < nm ? gload(post + (e >> gs)) : C{0, 0};
+      }
+#pragma unroll
+      for (int u = 0; u < FFT_SWEEP; ++u) {
+        const int e = e0 + u * NT;
+        if (e >= nm) continue;
+        const int s = e & (G - 1), m = e >> gs;
+        if (fb + s >= fend) continue;
+        const C zm = lds_load(lds_elem<C>(s * fs + m));
+        const C zr = cconj(lds_load(lds_elem<C>(s * fs + (m == 0 ? 0 : h - m))));
+        const C sm = cadd(zm, zr);
+        const C d = csub(zm, zr);
+        const C t = cmul(pm[u], d);
+        // X = sm/2 - (i/2) t
+        C x = C{(T)0.5 * (sm.x + t.y), (T)0.5 * (sm.y - t.x)};
+        if (m == 0) x = C{zm.x + zm.y, 0};
+        gstore(fc + ((rn.frow + m) * 2 + side) * (int64_t)p.Fp + fb + s, cscale(x, scale));
+      }
+    }
+    // the next transform's input sweep overwrites this one
+    __syncthreads();
   }
 }
 
-size_t fft_lds_bytes(int prec, int L, int mmax, int G) {
+size_t fft_lds_bytes(int prec, int L, int G) {
   const size_t c = (prec == SHT_FP64) ? 16 : 8;
-  return c * lds_slots((size_t)G * (lds_stride(L) + (mmax >= 0 ? (size_t)mmax + 1 : 0)));
+  return c * lds_slots((size_t)G * lds_stride(L));
 }
 
 // Kernels: work groups loop over the items (grid stride), one kernel per

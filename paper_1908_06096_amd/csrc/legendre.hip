@@ -256,6 +256,9 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
 // ---------------------------------------------------------------------------
 // Analysis: for m, output k tile [t0, t0 + BK) and real columns [c0, c0 + BC):
 //   a[m + 2k + par][c] = sum_r T_par[r][k] X_par[r][c],  X_0 = S, X_1 = A,
+// where S = N + S' and A = N - S' are formed as the operand is staged from
+// the two Fourier rows of north ring r: N (the ring's w chat) and S' (its
+// mirror's),
 // computed transposed (rows c, columns k) so that, in f32, each lane holds
 // the real and imaginary part of one coefficient.  The sum runs over the
 // north rings carrying m, KJ rings per iteration, with the next rings'
@@ -273,12 +276,12 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
   constexpr int WC = BC / WCW, WK = BK / WKW;
   constexpr int IC = WC / 16, IK = WK / 16;
   constexpr int CS = BC / VN;                 // vectors per X row segment
-  constexpr int XUNITS = 2 * KJ * CS;
-  constexpr int XU = XUNITS / 256;
+  constexpr int XUNITS = KJ * CS;             // (ring row, vector): both Fourier rows each
+  constexpr int XU = (XUNITS + 255) / 256;
   constexpr int NCH = BK / KCH;               // table chunks per parity
   constexpr int TUNITS = 2 * NCH * KJ;        // (parity, chunk, ring) units of KCH elements
   constexpr int TU = TUNITS / 256;
-  static_assert(XUNITS % 256 == 0 && TUNITS % 256 == 0 && KJ % 4 == 0, "tile shape");
+  static_assert((XUNITS % 256 == 0 || XUNITS < 256) && TUNITS % 256 == 0 && KJ % 4 == 0, "tile shape");
   __shared__ T Xs[2][KJ][BC + LDS_PAD];
   __shared__ T Ts[2][KJ][BK + LDS_PAD];
 
@@ -293,19 +296,21 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
   const int64_t rowlen = 2 * (int64_t)p.Fp;
   const int nj = (mi.L + KJ - 1) / KJ;
 
-  // X unit: (parity, ring row, column vector).  Rings past L read ring
-  // L - 1 (their table rows are the zero padding: steps of KJ rings never
-  // pass L rounded up to ROWPAD), columns past the row (outputs never
-  // stored) are clamped into it, and the Fourier row offsets of the next
-  // step's rings are looked up one step ahead.
-  int x_par[XU], x_rr[XU], x_c[XU], x_cg[XU];
+  // X unit: (ring row, column vector), loading the N and S' rows.  Rings
+  // past L read ring L - 1 (their table rows are the zero padding: steps of
+  // KJ rings never pass L rounded up to ROWPAD), columns past the row
+  // (outputs never stored) are clamped into it, and the Fourier row offsets
+  // of the next step's rings are looked up one step ahead.  With fewer
+  // units than threads the upper threads load nothing.
+  int x_rr[XU], x_c[XU], x_cg[XU];
+  bool x_on[XU];
 #pragma unroll
   for (int a = 0; a < XU; ++a) {
     const int u = tid + 256 * a;
+    x_on[a] = u < XUNITS;
     x_c[a] = (u % CS) * VN;
     x_cg[a] = min(it.c0 + x_c[a], 2 * p.Fp - VN);
     x_rr[a] = (u / CS) % KJ;
-    x_par[a] = u / (CS * KJ);
   }
   // table unit: (parity, chunk, ring row) through one descriptor per parity
   // (the parity is the same across a wave); chunks past the table read zero
@@ -327,11 +332,16 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
 #pragma unroll
     for (int a = 0; a < XU; ++a) dst[a] = gload(&p.rings[mi.first_ring + min(jc * KJ + x_rr[a], mi.L - 1)].frow);
   };
-  V rx[XU];
+  V rx[XU][2];
   V rt[TU][KCH / VN];
   auto fetch = [&](int jc) {
 #pragma unroll
-    for (int a = 0; a < XU; ++a) rx[a] = gload((const V*)(four + ((fr[a] + m) * 2 + x_par[a]) * rowlen + x_cg[a]));
+    for (int a = 0; a < XU; ++a) {
+      if (!x_on[a]) continue;
+      const T* row = four + ((fr[a] + m) * 2) * rowlen + x_cg[a];
+      rx[a][0] = gload((const V*)row);
+      rx[a][1] = gload((const V*)(row + rowlen));
+    }
     const uint32_t so = (uint32_t)jc * KJ * KCH * (uint32_t)sizeof(T);
 #pragma unroll
     for (int a = 0; a < TU; ++a) {
@@ -353,7 +363,11 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
   if (nj > 1) fetch_rows(1, fr_next);
   for (int jc = 0; jc < nj; ++jc) {
 #pragma unroll
-    for (int a = 0; a < XU; ++a) *(V*)&Xs[x_par[a]][x_rr[a]][x_c[a]] = rx[a];
+    for (int a = 0; a < XU; ++a) {
+      if (!x_on[a]) continue;
+      *(V*)&Xs[0][x_rr[a]][x_c[a]] = rx[a][0] + rx[a][1];  // S = N + S'
+      *(V*)&Xs[1][x_rr[a]][x_c[a]] = rx[a][0] - rx[a][1];  // A = N - S'
+    }
 #pragma unroll
     for (int a = 0; a < TU; ++a)
 #pragma unroll
@@ -686,7 +700,7 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   constexpr int WC = BC / 2, WK = BK / 2;
   constexpr int IC = WC / 16, IK = WK / 16;
   constexpr int NCH = BK / KCH;
-  static_assert(2 * (BC / 4) * (KJ / 8) == 256, "X units");
+  static_assert((BC / 4) * (KJ / 4) == 256, "X units");
   constexpr int TUNITS = 2 * NCH * (KJ / 8) * 2;  // (plane, parity, chunk, ring octet)
   static_assert(TUNITS <= 256, "table units");
   __shared__ __align__(16) u16 Xs[2][2][BC][KJ + BPAD];  // [plane][parity][col c][ring]
@@ -703,15 +717,16 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   const int64_t rowlen = 2 * (int64_t)p.Fp;
   const int nj = (mi.L + KJ - 1) / KJ;
 
-  // X unit: (parity, ring octet, column quad), the column quad fastest so
-  // that a load instruction covers two rings' 512-byte row segments (with
-  // the ring octet fastest it covered four rings' 256-byte segments, and
-  // the L1's tag lookups made the gather cost 30% more).  Rings past L are
-  // read at ring L - 1 (their table rows are zero or past the table), and
-  // columns past the row end (outputs never stored) are clamped into the row.
-  const int x_cq = tid % (BC / 4);
-  const int x_oct = (tid / (BC / 4)) % (KJ / 8);
-  const int x_par = tid / ((KJ / 8) * (BC / 4));
+  // X unit: (ring quad, column quad), the column quad fastest, so a load
+  // instruction covers two 512-byte row segments (with four rings' 256-byte
+  // segments per instruction the L1's tag lookups made the gather 30%
+  // slower).  A thread loads the N and S' rows of its 4 rings and forms
+  // S = N + S' and A = N - S'.  Rings past L are read at ring L - 1 (their
+  // table rows are zero or past the table), and columns past the row end
+  // (outputs never stored) are clamped into the row.
+  static_assert(BC / 4 == 32, "X units: 32 column quads");
+  const int x_cq = tid & 31;
+  const int x_q = tid >> 5;
   const int x_c = min(it.c0 + 4 * x_cq, 2 * p.Fp - 4);
   // table unit: (plane, parity, chunk, ring octet), read through one buffer
   // descriptor per (parity, plane): chunks past the table return zero
@@ -726,20 +741,23 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   const uint32_t t_off = ((uint32_t)(it.t0 / KCH + t_ch) * mi.Lp + 8u * t_oct) * (KCH * 2);
 
   // the Fourier rows of the rings of step jc + 1 are looked up one step ahead
-  int64_t fr[8], fr_next[8];
+  int64_t fr[4], fr_next[4];
   auto fetch_rows = [&](int jc, int64_t* dst) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = min(jc * KJ + 8 * x_oct + e, mi.L - 1);
+    for (int e = 0; e < 4; ++e) {
+      const int r = min(jc * KJ + 4 * x_q + e, mi.L - 1);
       dst[e] = gload(&p.rings[mi.first_ring + r].frow);
     }
   };
-  float4 rx[8];
+  float4 rx[4][2];  // [ring][N, S']
   uint4 rt[8];
   auto fetch = [&](int jc) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e)
-      rx[e] = gload((const float4*)(four + ((fr[e] + m) * 2 + x_par) * rowlen + x_c));
+    for (int e = 0; e < 4; ++e) {
+      const float* row = four + ((fr[e] + m) * 2) * rowlen + x_c;
+      rx[e][0] = gload((const float4*)row);
+      rx[e][1] = gload((const float4*)(row + rowlen));
+    }
     if (t_on) {
       const uint32_t so = (uint32_t)jc * KJ * (KCH * 2);
 #pragma unroll
@@ -760,19 +778,30 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   fetch(0);
   if (nj > 1) fetch_rows(1, fr_next);
   for (int jc = 0; jc < nj; ++jc) {
-    // X: 4 columns x 8 rings -> per column 8 rings of hi and lo
+    // X: 4 columns x 4 rings of S = N + S' and A = N - S' -> per column and
+    // parity 4 rings of hi and lo (half of an 8-ring operand unit)
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      uint32_t h[4], l[4];
+    for (int par = 0; par < 2; ++par) {
+      float4 x[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float4 u = rx[2 * e], w = rx[2 * e + 1];
-        const float a = cc == 0 ? u.x : cc == 1 ? u.y : cc == 2 ? u.z : u.w;
-        const float b = cc == 0 ? w.x : cc == 1 ? w.y : cc == 2 ? w.z : w.w;
-        split2_bf16(a, b, &h[e], &l[e]);
+        const float4 n = rx[e][0], s = rx[e][1];
+        x[e] = par ? make_float4(n.x - s.x, n.y - s.y, n.z - s.z, n.w - s.w)
+                   : make_float4(n.x + s.x, n.y + s.y, n.z + s.z, n.w + s.w);
       }
-      *(uint4*)&Xs[0][x_par][4 * x_cq + cc][8 * x_oct] = make_uint4(h[0], h[1], h[2], h[3]);
-      *(uint4*)&Xs[1][x_par][4 * x_cq + cc][8 * x_oct] = make_uint4(l[0], l[1], l[2], l[3]);
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc) {
+        uint32_t h[2], l[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const float4 u = x[2 * e], w = x[2 * e + 1];
+          const float a = cc == 0 ? u.x : cc == 1 ? u.y : cc == 2 ? u.z : u.w;
+          const float b = cc == 0 ? w.x : cc == 1 ? w.y : cc == 2 ? w.z : w.w;
+          split2_bf16(a, b, &h[e], &l[e]);
+        }
+        *(uint2*)&Xs[0][par][4 * x_cq + cc][4 * x_q] = make_uint2(h[0], h[1]);
+        *(uint2*)&Xs[1][par][4 * x_cq + cc][4 * x_q] = make_uint2(l[0], l[1]);
+      }
     }
     // table: 8 rings x 8 k (16-bit) -> 8 k x 8 rings
     {

@@ -190,8 +190,7 @@ struct DevPlan {
   int32_t N, nlat, nh, F, Fp;
   int64_t npts, nspec;
   const RingInfo* rings;
-  const FftClass* classes;      // synthesis work groups
-  const FftClass* classes_ana;  // analysis work groups (same lengths and tables)
+  const FftClass* classes;
   const MInfo* ms;
   const double* mu;
   const double* w;
@@ -208,9 +207,8 @@ struct DevPlan {
 hipError_t launch_gauss(int nlat, double* mu, double* w, hipStream_t s);
 hipError_t launch_pbar_planes(const DevPlan& p, int prec, const MInfo* d_ms, int nm, int max_Lp,
                               void* tab, int64_t plane_elems, hipStream_t s);
-// all of each class's tables, or (twiddles_only) only its twiddles
 hipError_t launch_fft_tables(const DevPlan& p, int prec, const FftClass* d_cls, int ncls,
-                             const FftClass* h_cls, void* fft, bool twiddles_only, hipStream_t s);
+                             const FftClass* h_cls, void* fft, hipStream_t s);
 hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& mi, int64_t plane,
                                       double* out, hipStream_t s);
 
@@ -234,9 +232,8 @@ hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, int tier, co
 hipError_t launch_fourier_analysis(const DevPlan* plans, int prec, int tier, const FftItem* items, int nitems,
                                    const IoBind* io, IoBind io0, size_t lds, int grid_blocks, hipStream_t s);
 hipError_t fft_set_max_lds(size_t bytes);
-// LDS of a work group of G transforms of length L; mmax >= 0 adds the
-// analysis' north results (mmax + 1 per field)
-size_t fft_lds_bytes(int prec, int L, int mmax, int G);
+// LDS of a work group of G transforms of length L
+size_t fft_lds_bytes(int prec, int L, int G);
 size_t fft_grid_blocks(int nitems);
 int fft_blocks_per_cu(int prec, int tier, size_t lds);
 

@@ -186,7 +186,7 @@ __device__ inline void put_c(T* base, int64_t i, double re, double im) {
 }
 
 template <typename T>
-__global__ void fft_tables_kernel(const FftClass* cls, T* fft, int twiddles_only) {
+__global__ void fft_tables_kernel(const FftClass* cls, T* fft) {
   const FftClass c = cls[blockIdx.x];
   const int L = c.L, h = c.h;
   int64_t off = c.root_off;
@@ -204,7 +204,6 @@ __global__ void fft_tables_kernel(const FftClass* cls, T* fft, int twiddles_only
     off += Ns * (R - 1);
     Ns = NR;
   }
-  if (twiddles_only) return;
   for (int q = threadIdx.x; q < h; q += blockDim.x) {
     double sn, cs;
     sincospi(-(double)q / (double)h, &sn, &cs);
@@ -235,15 +234,14 @@ __global__ void fft_tables_kernel(const FftClass* cls, T* fft, int twiddles_only
 }
 
 hipError_t launch_fft_tables(const DevPlan& p, int prec, const FftClass* d_cls, int ncls,
-                             const FftClass* h_cls, void* fft, bool twiddles_only, hipStream_t s) {
+                             const FftClass* h_cls, void* fft, hipStream_t s) {
   (void)p;
   (void)h_cls;
   if (ncls == 0) return hipSuccess;
   if (prec == SHT_FP64)
-    hipLaunchKernelGGL(fft_tables_kernel<double>, dim3(ncls), dim3(256), 0, s, d_cls, (double*)fft,
-                       (int)twiddles_only);
+    hipLaunchKernelGGL(fft_tables_kernel<double>, dim3(ncls), dim3(256), 0, s, d_cls, (double*)fft);
   else
-    hipLaunchKernelGGL(fft_tables_kernel<float>, dim3(ncls), dim3(256), 0, s, d_cls, (float*)fft, (int)twiddles_only);
+    hipLaunchKernelGGL(fft_tables_kernel<float>, dim3(ncls), dim3(256), 0, s, d_cls, (float*)fft);
   return hipGetLastError();
 }
 

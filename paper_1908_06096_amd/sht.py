@@ -304,8 +304,9 @@ class Plan:
         return torch.view_as_complex(t.view(self.nfour, self.fpad, 2))
 
     def analysis_fourier_view(self, workspace):
-        """Complex view [nfour/2, 2 (S, A), fpad] of the analysis-form workspace
-        (row index four_row[j] + m for north ring j)."""
+        """Complex view [nfour/2, 2, fpad] of the analysis-form workspace (row
+        index four_row[j] + m for north ring j; slot 0 the scaled
+        coefficients of ring j, slot 1 those of its mirror ring)."""
         import torch
 
         t = workspace[: self.nfour * self.fpad * 2 * self.info.elem_bytes].view(self.dtype)

@@ -71,7 +71,11 @@ def test_fourier_synthesis(sht, case):
         assert rel_l2(grid_t.cpu().numpy(), ref) <= TOL[prec]
 
 
-def _folded(geo, w, chat):
+def _analysis_form(geo, w, chat):
+    """The analysis form of the Fourier workspace from the oracle's per-ring
+    coefficients: slot 0 the weighted coefficients of north ring j, slot 1
+    those of its mirror ring (the direct Legendre stage folds them into
+    S = slot 0 + slot 1 and A = slot 0 - slot 1)."""
     nh = geo["nlat"] // 2
     F = chat.shape[0]
     out = np.zeros((geo["nfour"] // 2, 2, F), dtype=np.complex128)
@@ -80,8 +84,8 @@ def _folded(geo, w, chat):
         a = chat[:, geo["foff"][j]:geo["foff"][j + 1]]
         b = chat[:, geo["foff"][js]:geo["foff"][js + 1]]
         r0 = geo["foff"][j]
-        out[r0:r0 + a.shape[1], 0] = (w[j] * (a + b)).T
-        out[r0:r0 + a.shape[1], 1] = (w[j] * (a - b)).T
+        out[r0:r0 + a.shape[1], 0] = (w[j] * a).T
+        out[r0:r0 + a.shape[1], 1] = (w[js] * b).T
     return out
 
 
@@ -97,7 +101,7 @@ def test_fourier_analysis(sht, case):
         torch.cuda.synchronize()
         got = plan.analysis_fourier_view(ws)[:, :, :F].cpu().numpy()
         chat, _s = oracle.direct(grid_np, N, grid)
-        ref = _folded(geo, w, chat)
+        ref = _analysis_form(geo, w, chat)
         assert rel_l2(got, ref) <= TOL[prec]
         # m = 0 entries are real
         nh = geo["nlat"] // 2
@@ -113,7 +117,7 @@ def test_legendre_direct(sht, case):
         _mu, w = oracle.gauss_newton(geo["nlat"])
         _g, gnp = grid_inputs(plan, seed=5)
         chat, spec_ref = oracle.direct(gnp, N, grid)
-        folded = _folded(geo, w, chat)
+        folded = _analysis_form(geo, w, chat)
         if prec != "fp64":
             folded = folded.astype(np.complex64).astype(np.complex128)
         ws = plan.empty_workspace()
