@@ -41,8 +41,16 @@ bool five_smooth(int64_t x) {
   return x == 1;
 }
 
-// Radices the passes can use (each has a register butterfly).
-constexpr int kRadices[] = {20, 18, 16, 15, 12, 10, 9, 8, 6, 5, 4, 3, 2};
+// A length the passes can factor: no prime factor above 19.
+bool radix_smooth(int64_t x) {
+  if (x < 1) return false;
+  for (int p : {2, 3, 5, 7, 11, 13, 17, 19})
+    while (x % p == 0) x /= p;
+  return x == 1;
+}
+
+// Radices the passes can use (each has a register butterfly), larger first.
+constexpr int kRadices[] = {20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
 
 // A pass of radix R over L points fits `threads` threads when its L / R
 // butterflies fit the FFT_REGS / R butterflies each thread holds.
@@ -68,7 +76,8 @@ int fewest_passes(int L, int x, int threads, std::map<int, std::pair<int, int>>*
   return bp;
 }
 
-// Radix sequence for a 5-smooth length: the fewest passes that all fit
+// Radix sequence for a length without prime factors above 19 (the chirp-z
+// lengths are 5-smooth): the fewest passes that all fit
 // `threads` threads, the larger radix first among equally short sequences.
 // Each pass is one LDS round trip and two barriers, which is what the
 // transforms' time goes to.  Empty when no sequence fits.
@@ -408,7 +417,7 @@ int build_host(sht_plan_s* p) {
   for (int h : hs) {
     FftClass c{};
     c.h = h;
-    if (five_smooth(h)) {
+    if (radix_smooth(h) && !radices(h).empty()) {
       c.L = h;
       c.bluestein = 0;
     } else {

@@ -4,8 +4,8 @@
 //
 // A ring of n = 2h points is transformed as a complex DFT of length h of
 // z_t = g_{2t} + i g_{2t+1} plus an O(h) pre/post step.  The complex DFT is
-// an in-LDS Stockham autosort FFT with radices 2, 3, 4, 5 when h is
-// 5-smooth; otherwise it is the chirp-z (Bluestein) identity
+// an in-LDS Stockham autosort FFT when h has no prime factor above 19 (the
+// largest prime radix); otherwise it is the chirp-z (Bluestein) identity
 //   X_q = c_q sum_t (z_t c_t) conj(c_{q-t}),  c_t = exp(-i pi t^2 / h),
 // evaluated as a cyclic convolution of 5-smooth length L >= 2h - 1 with two
 // more FFTs.  Inverse DFTs use conj(DFT(conj(x))).
@@ -169,9 +169,63 @@ __device__ inline void butterfly_ct(typename V2T<T>::type* v) {
   }
 }
 
+// cos and sin of 2 pi j / P for j < P, evaluated by the front end (a
+// constexpr object), so that the unrolled butterflies below index constants
+// rather than expanding unit_root's series P^2 / 4 times.
+template <int P>
+struct RootTable {
+  double c[P], s[P];
+  constexpr RootTable() : c(), s() {
+    for (int j = 0; j < P; ++j) {
+      const UnitRoot r = unit_root(j, P);
+      c[j] = r.c;
+      s[j] = r.s;
+    }
+  }
+};
+
+// DFT of an odd prime number P of points.  With the pairs
+// u_j = x_j + x_{P-j} and v_j = x_j - x_{P-j} (1 <= j <= H = (P - 1) / 2),
+//   X_0 = x_0 + sum_j u_j,
+//   X_k = a_k - i b_k and X_{P-k} = a_k + i b_k (1 <= k <= H), where
+//   a_k = x_0 + sum_j cos(2 pi j k / P) u_j and b_k = sum_j sin(2 pi j k / P) v_j:
+// 4 H^2 real multiply-adds, with the cosines and sines folded to immediates.
+template <typename T, int P>
+__device__ inline void butterfly_odd(typename V2T<T>::type* v) {
+  typedef typename V2T<T>::type C;
+  constexpr int H = (P - 1) / 2;
+  C u[H], w[H];
+#pragma unroll
+  for (int j = 1; j <= H; ++j) {
+    u[j - 1] = cadd(v[j], v[P - j]);
+    w[j - 1] = csub(v[j], v[P - j]);
+  }
+  constexpr RootTable<P> rt{};
+  const C x0 = v[0];
+  C s0 = x0;
+#pragma unroll
+  for (int j = 0; j < H; ++j) s0 = cadd(s0, u[j]);
+#pragma unroll
+  for (int k = 1; k <= H; ++k) {
+    C a = x0, b = C{0, 0};
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+      const T cjk = (T)rt.c[(j * k) % P], sjk = (T)rt.s[(j * k) % P];
+      a.x += cjk * u[j - 1].x;
+      a.y += cjk * u[j - 1].y;
+      b.x += sjk * w[j - 1].x;
+      b.y += sjk * w[j - 1].y;
+    }
+    v[k] = cadd(a, cmul_negi(b));
+    v[P - k] = csub(a, cmul_negi(b));
+  }
+  v[0] = s0;
+}
+
 // Forward DFT of R points in registers.  Radices 2, 3, 4 and 5 are written
-// out; 8 and 16 take one even/odd step, 9 a 3 x 3 step, and the composite
-// radices 6, 10, 12, 15, 18 and 20 the generic step above.
+// out; 8 and 16 take one even/odd step, 9 a 3 x 3 step, the primes 7, 11,
+// 13, 17 and 19 the pair form above, and the composite radices 6, 10, 12,
+// 14, 15, 18 and 20 the generic step above.
 template <typename T, int R>
 __device__ inline void butterfly(typename V2T<T>::type* v) {
   typedef typename V2T<T>::type C;
@@ -262,12 +316,16 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
       v[k1 + 3] = t[1];
       v[k1 + 6] = t[2];
     }
+  } else if constexpr (R == 7 || R == 11 || R == 13 || R == 17 || R == 19) {
+    butterfly_odd<T, R>(v);
   } else if constexpr (R == 6) {
     butterfly_ct<T, 3, 2>(v);
   } else if constexpr (R == 10) {
     butterfly_ct<T, 5, 2>(v);
   } else if constexpr (R == 12) {
     butterfly_ct<T, 4, 3>(v);
+  } else if constexpr (R == 14) {
+    butterfly_ct<T, 7, 2>(v);
   } else if constexpr (R == 15) {
     butterfly_ct<T, 5, 3>(v);
   } else if constexpr (R == 18) {
@@ -361,6 +419,19 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
                                      const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                      typename V2T<T>::type* io, int h, int lt, int nt) {
 #define SHT_PASS(RR) stockham_pass<T, RR, MODE>(e0, L, Ns, tw, aux, io, h, lt, nt)
+  // radices with a factor above 5 occur only in plain transforms of length h
+  // (the chirp-z lengths are 5-smooth)
+  if constexpr (MODE == OUT_PLAIN || MODE == OUT_GRID) {
+    switch (R) {
+      case 19: SHT_PASS(19); return;
+      case 17: SHT_PASS(17); return;
+      case 14: SHT_PASS(14); return;
+      case 13: SHT_PASS(13); return;
+      case 11: SHT_PASS(11); return;
+      case 7: SHT_PASS(7); return;
+      default: break;
+    }
+  }
   switch (R) {
     case 20: SHT_PASS(20); break;
     case 18: SHT_PASS(18); break;

@@ -122,8 +122,8 @@ struct RingInfo {
 
 // One FFT class per distinct half length h = nlon / 2.  The real DFT of
 // length 2h is carried out as a complex DFT of length h; when h has a prime
-// factor above 5 that DFT is a chirp-z convolution of length L (5-smooth,
-// L >= 2h - 1), otherwise L = h.
+// factor above 19 (the largest prime radix) that DFT is a chirp-z
+// convolution of length L (5-smooth, L >= 2h - 1), otherwise L = h.
 struct FftClass {
   int32_t h;
   int32_t L;

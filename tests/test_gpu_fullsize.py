@@ -51,9 +51,30 @@ def _grid(plan, seed):
     return t, g.astype(np.float64)
 
 
-def _rings(nlat):
+def _largest_prime(x):
+    big, q = 1, 2
+    while q * q <= x:
+        while x % q == 0:
+            big, x = q, x // q
+        q += 1
+    return max(big, x) if x > 1 else big
+
+
+def _rings(geo):
+    """Poles, equator, a ring in between, and on octahedral grids the longest
+    southern-hemisphere rings whose half length's largest prime factor is 7,
+    11, 13, 17 and 19 (transforms whose passes take those prime radices)."""
+    nlat = geo["nlat"]
     nh = nlat // 2
-    return sorted({0, 1, nlat // 5, nh - 1, nh, nlat - 2, nlat - 1})
+    rings = {0, 1, nlat // 5, nh - 1, nh, nlat - 2, nlat - 1}
+    if geo["grid"] == "octahedral":
+        want = {7, 11, 13, 17, 19}
+        for j in range(nh, nlat):
+            p = _largest_prime(int(geo["nlon"][j]) // 2)
+            if p in want:
+                want.discard(p)
+                rings.add(j)
+    return sorted(rings)
 
 
 @pytest.mark.parametrize("case", CASES, ids=_ids)
@@ -64,7 +85,7 @@ def test_full_size_sampled(sht, case):
         # synthesis on sampled rings
         spec_t, spec_c = _spec(plan, seed=21)
         g = plan.inverse(spec_t)
-        rings = _rings(geo["nlat"])
+        rings = _rings(geo)
         _four, ref = oracle.inverse(spec_c, N, grid, rings=rings)
         got, want = [], []
         for fo in FIELDS:
