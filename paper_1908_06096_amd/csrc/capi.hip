@@ -41,31 +41,36 @@ bool five_smooth(int64_t x) {
   return x == 1;
 }
 
-// A length the passes can factor: no prime factor above 19.
+// A length the passes can factor: no prime factor above 23, the largest
+// prime radix.  (Primes up to 47 were measured: their butterflies need all
+// 128 registers of an FP32 pass, which makes the kernels around the passes
+// spill, and the FFT stages came out slower than with 23.)
 bool radix_smooth(int64_t x) {
   if (x < 1) return false;
-  for (int p : {2, 3, 5, 7, 11, 13, 17, 19})
+  for (int p : {2, 3, 5, 7, 11, 13, 17, 19, 23})
     while (x % p == 0) x /= p;
   return x == 1;
 }
 
 // Radices the passes can use (each has a register butterfly), larger first.
-constexpr int kRadices[] = {20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+constexpr int kRadices[] = {23, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
 
 // A pass of radix R over L points fits `threads` threads when its L / R
-// butterflies fit the FFT_REGS / R butterflies each thread holds.
+// butterflies fit the FFT_REGS / R butterflies each thread holds (one for
+// the prime radices above FFT_REGS).
 bool radix_fits(int L, int R, int threads) {
-  return (int64_t)(L / R) <= (int64_t)(FFT_REGS / R) * threads;
+  return (int64_t)(L / R) <= (int64_t)std::max(1, FFT_REGS / R) * threads;
 }
 
 // Fewest passes for the cofactor x of L (memoised), and the first radix.
+// Radices above FFT_REGS are taken for the first pass only (x = L).
 int fewest_passes(int L, int x, int threads, std::map<int, std::pair<int, int>>* memo) {
   if (x == 1) return 0;
   auto it = memo->find(x);
   if (it != memo->end()) return it->second.first;
   int bp = 1 << 20, br = 0;
   for (int R : kRadices)
-    if (x % R == 0 && radix_fits(L, R, threads)) {
+    if (x % R == 0 && (R <= FFT_REGS || x == L) && radix_fits(L, R, threads)) {
       const int c = 1 + fewest_passes(L, x / R, threads, memo);
       if (c < bp) {
         bp = c;
@@ -76,7 +81,7 @@ int fewest_passes(int L, int x, int threads, std::map<int, std::pair<int, int>>*
   return bp;
 }
 
-// Radix sequence for a length without prime factors above 19 (the chirp-z
+// Radix sequence for a length without prime factors above 23 (the chirp-z
 // lengths are 5-smooth): the fewest passes that all fit
 // `threads` threads, the larger radix first among equally short sequences.
 // Each pass is one LDS round trip and two barriers, which is what the

@@ -4,7 +4,7 @@
 //
 // A ring of n = 2h points is transformed as a complex DFT of length h of
 // z_t = g_{2t} + i g_{2t+1} plus an O(h) pre/post step.  The complex DFT is
-// an in-LDS Stockham autosort FFT when h has no prime factor above 19 (the
+// an in-LDS Stockham autosort FFT when h has no prime factor above 23 (the
 // largest prime radix); otherwise it is the chirp-z (Bluestein) identity
 //   X_q = c_q sum_t (z_t c_t) conj(c_{q-t}),  c_t = exp(-i pi t^2 / h),
 // evaluated as a cyclic convolution of 5-smooth length L >= 2h - 1 with two
@@ -190,21 +190,25 @@ struct RootTable {
 //   X_k = a_k - i b_k and X_{P-k} = a_k + i b_k (1 <= k <= H), where
 //   a_k = x_0 + sum_j cos(2 pi j k / P) u_j and b_k = sum_j sin(2 pi j k / P) v_j:
 // 4 H^2 real multiply-adds, with the cosines and sines folded to immediates.
-template <typename T, int P>
-__device__ inline void butterfly_odd(typename V2T<T>::type* v) {
+// Each output pair goes to emit(k, X_k) as soon as it is formed, so a pass
+// can store it at once and hold only the pairs and two outputs (about P
+// complex values) rather than all P outputs beside the pairs.
+template <typename T, int P, typename E>
+__device__ inline void butterfly_odd_emit(const typename V2T<T>::type* v, E&& emit) {
   typedef typename V2T<T>::type C;
   constexpr int H = (P - 1) / 2;
+  constexpr RootTable<P> rt{};
   C u[H], w[H];
 #pragma unroll
   for (int j = 1; j <= H; ++j) {
     u[j - 1] = cadd(v[j], v[P - j]);
     w[j - 1] = csub(v[j], v[P - j]);
   }
-  constexpr RootTable<P> rt{};
   const C x0 = v[0];
   C s0 = x0;
 #pragma unroll
   for (int j = 0; j < H; ++j) s0 = cadd(s0, u[j]);
+  emit(0, s0);
 #pragma unroll
   for (int k = 1; k <= H; ++k) {
     C a = x0, b = C{0, 0};
@@ -216,15 +220,24 @@ __device__ inline void butterfly_odd(typename V2T<T>::type* v) {
       b.x += sjk * w[j - 1].x;
       b.y += sjk * w[j - 1].y;
     }
-    v[k] = cadd(a, cmul_negi(b));
-    v[P - k] = csub(a, cmul_negi(b));
+    emit(k, cadd(a, cmul_negi(b)));
+    emit(P - k, csub(a, cmul_negi(b)));
   }
-  v[0] = s0;
+}
+
+template <typename T, int P>
+__device__ inline void butterfly_odd(typename V2T<T>::type* v) {
+  typedef typename V2T<T>::type C;
+  butterfly_odd_emit<T, P>(v, [&](int r, const C& y) { v[r] = y; });
+}
+
+__host__ __device__ constexpr bool odd_prime_radix(int R) {
+  return R == 7 || R == 11 || R == 13 || R == 17 || R == 19 || R == 23;
 }
 
 // Forward DFT of R points in registers.  Radices 2, 3, 4 and 5 are written
-// out; 8 and 16 take one even/odd step, 9 a 3 x 3 step, the primes 7, 11,
-// 13, 17 and 19 the pair form above, and the composite radices 6, 10, 12,
+// out; 8 and 16 take one even/odd step, 9 a 3 x 3 step, the odd primes
+// from 7 to 23 the pair form above, and the composite radices 6, 10, 12,
 // 14, 15, 18 and 20 the generic step above.
 template <typename T, int R>
 __device__ inline void butterfly(typename V2T<T>::type* v) {
@@ -316,7 +329,7 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
       v[k1 + 3] = t[1];
       v[k1 + 6] = t[2];
     }
-  } else if constexpr (R == 7 || R == 11 || R == 13 || R == 17 || R == 19) {
+  } else if constexpr (odd_prime_radix(R)) {
     butterfly_odd<T, R>(v);
   } else if constexpr (R == 6) {
     butterfly_ct<T, 3, 2>(v);
@@ -360,7 +373,11 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                            typename V2T<T>::type* io, int h, int lt, int nt) {
   typedef typename V2T<T>::type C;
-  constexpr int MAXB = FFT_REGS / R;
+  // a radix above FFT_REGS (a prime) runs as the first pass only (the plan
+  // sees to it): Ns = 1, no twiddles, one butterfly per thread
+  constexpr bool FIRST = R > FFT_REGS;
+  constexpr int MAXB = FIRST ? 1 : FFT_REGS / R;
+  if constexpr (FIRST) Ns = 1;
   const int nb = L / R;
   // b mod Ns by multiply-high: for b < 2^14 and 1 < Ns <= 2^13,
   // floor(b / Ns) = umulhi(b, ceil(2^32 / Ns)) exactly
@@ -378,7 +395,7 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
     if (b < nb) {
 #pragma unroll
       for (int r = 0; r < R; ++r) v[i][r] = lds_load(lds_elem<C>(e0 + (uint32_t)(b + r * nb)));
-      if (Ns > 1) {
+      if (!FIRST && Ns > 1) {
         const uint32_t t = (uint32_t)(kk[i] * (R - 1)) * (uint32_t)sizeof(C);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], buffer_load<C>(trs, t + (r - 1) * sizeof(C)));
@@ -390,24 +407,29 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
   for (int i = 0; i < MAXB; ++i) {
     const int b = lt + i * nt;
     if (b < nb) {
-      butterfly<T, R>(v[i]);
       const int k = kk[i];
       const int d = (b - k) * R + k;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
+      auto emit = [&](int r, const C& y) {
         const int o = d + r * Ns;
         const uint32_t ao = (uint32_t)o * (uint32_t)sizeof(C);
         if constexpr (MODE == OUT_PLAIN) {
-          lds_store(lds_elem<C>(e0 + (uint32_t)o), v[i][r]);
+          lds_store(lds_elem<C>(e0 + (uint32_t)o), y);
         } else if constexpr (MODE == OUT_KHAT) {
-          lds_store(lds_elem<C>(e0 + (uint32_t)o), cconj(cmul(v[i][r], buffer_load<C>(ars, ao))));
+          lds_store(lds_elem<C>(e0 + (uint32_t)o), cconj(cmul(y, buffer_load<C>(ars, ao))));
         } else if constexpr (MODE == OUT_CHIRP) {
-          if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), cmul(buffer_load<C>(ars, ao), cconj(v[i][r])));
+          if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), cmul(buffer_load<C>(ars, ao), cconj(y)));
         } else if constexpr (MODE == OUT_GRID) {
-          if (io && o < h) gstore(io + o, cconj(v[i][r]));
+          if (io && o < h) gstore(io + o, cconj(y));
         } else {
-          if (io && o < h) gstore(io + o, cmul(cconj(buffer_load<C>(ars, ao)), v[i][r]));
+          if (io && o < h) gstore(io + o, cmul(cconj(buffer_load<C>(ars, ao)), y));
         }
+      };
+      if constexpr (odd_prime_radix(R)) {
+        butterfly_odd_emit<T, R>(v[i], emit);
+      } else {
+        butterfly<T, R>(v[i]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) emit(r, v[i][r]);
       }
     }
   }
@@ -423,6 +445,7 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
   // (the chirp-z lengths are 5-smooth)
   if constexpr (MODE == OUT_PLAIN || MODE == OUT_GRID) {
     switch (R) {
+      case 23: SHT_PASS(23); return;
       case 19: SHT_PASS(19); return;
       case 17: SHT_PASS(17); return;
       case 14: SHT_PASS(14); return;

@@ -26,7 +26,8 @@ constexpr int ROWPAD = 32;
 constexpr int FPAD = 16;
 
 // FFT: threads per work group and complex values each thread may hold in
-// registers during one pass; together they bound the transform length.
+// registers during one pass (or one butterfly of a prime radix above it);
+// together they bound the transform length.
 // Transforms run in work groups of FFT_THREADS_SMALL threads (tier 0) where
 // that many threads per field cover every pass with the fewest passes, else
 // of FFT_THREADS (tier 1): smaller groups wait at smaller barriers and more
@@ -122,7 +123,7 @@ struct RingInfo {
 
 // One FFT class per distinct half length h = nlon / 2.  The real DFT of
 // length 2h is carried out as a complex DFT of length h; when h has a prime
-// factor above 19 (the largest prime radix) that DFT is a chirp-z
+// factor above 23 (the largest prime radix) that DFT is a chirp-z
 // convolution of length L (5-smooth, L >= 2h - 1), otherwise L = h.
 struct FftClass {
   int32_t h;
