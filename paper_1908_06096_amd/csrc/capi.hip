@@ -86,17 +86,37 @@ int fewest_passes(int L, int x, int threads, std::map<int, std::pair<int, int>>*
 // `threads` threads, the larger radix first among equally short sequences.
 // Each pass is one LDS round trip and two barriers, which is what the
 // transforms' time goes to.  Empty when no sequence fits.
-std::vector<int> radices(int L, int threads = FFT_THREADS) {
+// With `palindrome` the first and last radices are equal: a chirp-z class
+// runs the sequence twice and fuses the last pass of the first transform
+// with the first pass of the second.
+std::vector<int> radices(int L, int threads = FFT_THREADS, bool palindrome = false) {
   std::map<int, std::pair<int, int>> memo;
   std::vector<int> r;
-  if (fewest_passes(L, L, threads, &memo) >= (1 << 20)) return r;
-  for (int x = L; x > 1; x /= memo[x].second) r.push_back(memo[x].second);
+  if (!palindrome) {
+    if (fewest_passes(L, L, threads, &memo) >= (1 << 20)) return r;
+    for (int x = L; x > 1; x /= memo[x].second) r.push_back(memo[x].second);
+    return r;
+  }
+  int best = 1 << 20, ba = 0;
+  for (int a : kRadices) {
+    if (a > FFT_REGS || L % (a * a) != 0 || !radix_fits(L, a, threads)) continue;
+    const int n = 2 + fewest_passes(L, L / (a * a), threads, &memo);
+    if (n < best) {
+      best = n;
+      ba = a;
+    }
+  }
+  if (ba == 0) return r;
+  r.push_back(ba);
+  for (int x = L / (ba * ba); x > 1; x /= memo[x].second) r.push_back(memo[x].second);
+  r.push_back(ba);
   return r;
 }
 
 // Chirp-z length for half length h: among the 5-smooth L >= 2h - 1 (up to a
-// quarter above), the one with the least L (passes + 1), the LDS traffic of
-// the two transforms and their element-wise steps.  0 when none fits.
+// quarter above) with a palindromic radix sequence of p passes, the one with
+// the least L (2p - 1), the LDS traffic of the two transforms with their
+// middle passes fused.  0 when none fits.
 int bluestein_length(int h) {
   const int64_t lo = 2 * (int64_t)h - 1;
   const int64_t hi = lo + std::max<int64_t>(64, lo / 4);
@@ -104,9 +124,9 @@ int bluestein_length(int h) {
   double best_cost = 0;
   for (int64_t L = lo; L <= hi && L < (1 << 14); ++L) {
     if (!five_smooth(L)) continue;
-    const std::vector<int> r = radices((int)L);
+    const std::vector<int> r = radices((int)L, FFT_THREADS, true);
     if (r.empty()) continue;
-    const double cost = (double)L * (double)(r.size() + 1);
+    const double cost = (double)L * (double)(2 * r.size() - 1);
     if (best == 0 || cost < best_cost) {
       best = (int)L;
       best_cost = cost;
@@ -316,7 +336,7 @@ void choose_groups(int prec, std::vector<FftClass>* cls) {
   auto lds = [&](const FftClass& c, int G) { return fft_lds_bytes(prec, c.L, G); };
   const int full = fft_blocks_per_cu(prec, 0, 0);
   for (FftClass& c : *cls) {
-    const std::vector<int> rs = radices(c.L, FFT_THREADS_SMALL);
+    const std::vector<int> rs = radices(c.L, FFT_THREADS_SMALL, c.bluestein);
     c.tier = (!rs.empty() && (int)rs.size() == c.nrad && fft_blocks_per_cu(prec, 0, lds(c, 1)) >= full) ? 0 : 1;
     if (c.tier == 0)
       for (size_t q = 0; q < rs.size(); ++q) c.rad[q] = rs[q];
@@ -340,7 +360,7 @@ void choose_groups(int prec, std::vector<FftClass>* cls) {
     std::vector<int> best(c.rad, c.rad + c.nrad);
     for (int s = 0; (2 << s) <= FFT_MAX_G; ++s) {
       const int G = 2 << s;
-      const std::vector<int> rad = radices(c.L, threads / G);
+      const std::vector<int> rad = radices(c.L, threads / G, c.bluestein);
       if (rad.empty() || rad.size() > (size_t)c.nrad) break;
       if (lds(c, G) > budget[c.tier]) break;
       gs = s + 1;
@@ -429,8 +449,9 @@ int build_host(sht_plan_s* p) {
       c.L = bluestein_length(h);
       c.bluestein = 1;
     }
-    std::vector<int> rad = c.L > 0 ? radices(c.L) : std::vector<int>();
-    if (rad.empty() || (int)rad.size() > FFT_MAX_RADICES) return SHT_EUNSUPPORTED;
+    std::vector<int> rad = c.L > 0 ? radices(c.L, FFT_THREADS, c.bluestein) : std::vector<int>();
+    // a chirp-z transform fuses its middle passes, which takes two passes
+    if (rad.empty() || (int)rad.size() > FFT_MAX_RADICES || (c.bluestein && rad.size() < 2)) return SHT_EUNSUPPORTED;
     c.nrad = (int)rad.size();
     for (size_t q = 0; q < rad.size(); ++q) c.rad[q] = rad[q];
     c.root_off = off;

@@ -351,7 +351,7 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
 }
 
 // What the last pass of a transform does with its outputs.
-enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2, OUT_GRID = 3, OUT_GRID_CHIRP = 4 };
+enum PassOut { OUT_PLAIN = 0, OUT_CHIRP = 1, OUT_GRID = 2, OUT_GRID_CHIRP = 3 };
 
 // One Stockham pass of radix R over L points in LDS, after Ns points have
 // been combined, carried out by the nt threads (thread lt) that own this
@@ -360,8 +360,8 @@ enum PassOut { OUT_PLAIN = 0, OUT_KHAT = 1, OUT_CHIRP = 2, OUT_GRID = 3, OUT_GRI
 // (b mod Ns)(R - 1) + r - 1, so lanes with consecutive b read consecutive
 // entries) and writes y[(b / Ns) Ns R + b mod Ns + r Ns].  All reads of the
 // pass land in registers before the barrier, so one LDS buffer suffices.
-//   OUT_KHAT stores conj(y khat), OUT_CHIRP stores c_q conj(y_q) for q < h
-//     (the element-wise steps of the chirp-z convolution);
+//   OUT_CHIRP stores c_q conj(y_q) for q < h (the last element-wise step
+//     of the chirp-z convolution);
 //   OUT_GRID writes conj(y_q) and OUT_GRID_CHIRP writes conj(c_q) y_q, the
 //     conjugate of what OUT_PLAIN and OUT_CHIRP would store, for q < h to
 //     io in device memory (nothing when io is null).
@@ -414,8 +414,6 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
         const uint32_t ao = (uint32_t)o * (uint32_t)sizeof(C);
         if constexpr (MODE == OUT_PLAIN) {
           lds_store(lds_elem<C>(e0 + (uint32_t)o), y);
-        } else if constexpr (MODE == OUT_KHAT) {
-          lds_store(lds_elem<C>(e0 + (uint32_t)o), cconj(cmul(y, buffer_load<C>(ars, ao))));
         } else if constexpr (MODE == OUT_CHIRP) {
           if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), cmul(buffer_load<C>(ars, ao), cconj(y)));
         } else if constexpr (MODE == OUT_GRID) {
@@ -473,20 +471,91 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
 #undef SHT_PASS
 }
 
-// Forward DFT of L points held in LDS (natural order in and out); the last
-// pass applies MODE with aux and io.
+// Passes q0 <= q < q1 of a forward DFT of L points held in LDS, starting
+// after Ns points have been combined with tw at pass q0's table; the last of
+// them applies MODE with aux and io.  All passes from Ns = 1: natural order
+// in and out.
 template <typename T, int MODE>
-__device__ __forceinline__ void fft_lds(uint32_t e0, int L, int nrad, const int32_t* rad,
-                                        const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
-                                        typename V2T<T>::type* io, int h, int lt, int nt) {
-  int Ns = 1;
-  for (int q = 0; q < nrad; ++q) {
+__device__ __forceinline__ void fft_passes(uint32_t e0, int L, const int32_t* rad, int q0, int q1, int Ns,
+                                           const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
+                                           typename V2T<T>::type* io, int h, int lt, int nt) {
+  for (int q = q0; q < q1; ++q) {
     const int R = gload(rad + q);
-    if (q == nrad - 1) pass_dispatch<T, MODE>(R, e0, L, Ns, tw, aux, io, h, lt, nt);
+    if (q == q1 - 1) pass_dispatch<T, MODE>(R, e0, L, Ns, tw, aux, io, h, lt, nt);
     else pass_dispatch<T, OUT_PLAIN>(R, e0, L, Ns, tw, nullptr, nullptr, h, lt, nt);
     tw += Ns * (R - 1);
     Ns *= R;
   }
+}
+
+// The middle of the chirp-z convolution: the last pass of the forward
+// transform (radix R, after Ns = L / R points), the element-wise step
+// B = conj(A khat), and the first pass of the second transform, which runs
+// the same radix sequence, whose first radix is also R (the plan gives
+// chirp-z classes palindromic sequences), at Ns = 1.
+// Butterfly b of both passes covers the elements b + r L/R (r < R): the
+// first pass writes them and the second reads them, so one thread takes
+// both in registers, with no LDS round trip or barrier in between, and
+// writes y[b R + r].  The twiddles exp(-2 pi i r b / L) are the first
+// pass's (b < Ns).
+template <typename T, int R>
+__device__ __noinline__ void chirp_middle_pass(uint32_t e0, int L, const typename V2T<T>::type* tw,
+                                               const typename V2T<T>::type* khat, int lt, int nt) {
+  typedef typename V2T<T>::type C;
+  constexpr int MAXB = FFT_REGS / R;
+  const int nb = L / R;
+  const __amdgpu_buffer_rsrc_t trs = buffer_rsrc(tw);
+  const __amdgpu_buffer_rsrc_t krs = buffer_rsrc(khat);
+  C v[MAXB][R];
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int b = lt + i * nt;
+    if (b < nb) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[i][r] = lds_load(lds_elem<C>(e0 + (uint32_t)(b + r * nb)));
+      const uint32_t t = (uint32_t)(b * (R - 1)) * (uint32_t)sizeof(C);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], buffer_load<C>(trs, t + (r - 1) * sizeof(C)));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < MAXB; ++i) {
+    const int b = lt + i * nt;
+    if (b < nb) {
+      butterfly<T, R>(v[i]);
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        v[i][r] = cconj(cmul(v[i][r], buffer_load<C>(krs, (uint32_t)(b + r * nb) * (uint32_t)sizeof(C))));
+      butterfly<T, R>(v[i]);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds_store(lds_elem<C>(e0 + (uint32_t)(b * R + r)), v[i][r]);
+    }
+  }
+  __syncthreads();
+}
+
+// The chirp-z lengths are 5-smooth.
+template <typename T>
+__device__ __forceinline__ void middle_dispatch(int R, uint32_t e0, int L, const typename V2T<T>::type* tw,
+                                                const typename V2T<T>::type* khat, int lt, int nt) {
+#define SHT_MID(RR) chirp_middle_pass<T, RR>(e0, L, tw, khat, lt, nt)
+  switch (R) {
+    case 20: SHT_MID(20); break;
+    case 18: SHT_MID(18); break;
+    case 16: SHT_MID(16); break;
+    case 15: SHT_MID(15); break;
+    case 12: SHT_MID(12); break;
+    case 10: SHT_MID(10); break;
+    case 9: SHT_MID(9); break;
+    case 8: SHT_MID(8); break;
+    case 6: SHT_MID(6); break;
+    case 5: SHT_MID(5); break;
+    case 4: SHT_MID(4); break;
+    case 3: SHT_MID(3); break;
+    default: SHT_MID(2); break;
+  }
+#undef SHT_MID
 }
 
 // Forward complex DFT of length h.  Input: z_t, t < h, in LDS at
@@ -494,17 +563,24 @@ __device__ __forceinline__ void fft_lds(uint32_t e0, int L, int nrad, const int3
 // entries h <= t < L must be zero.  Output: Z_q, q < h, in LDS at element
 // e0 + q, or with GRID_OUT its conjugate written to io (nothing
 // when io is null).  Chirp-z: A = DFT_L(a), B = conj(A khat),
-// Z_q = c_q conj(DFT_L(B))_q.
+// Z_q = c_q conj(DFT_L(B))_q.  The radix sequence begins and ends with the
+// same radix, so the second DFT's first pass fuses with the first DFT's
+// last (a chirp-z length exceeds the largest radix, so each DFT has at
+// least two passes).
 template <typename T, bool GRID_OUT>
 __device__ __forceinline__ void dft_h(uint32_t e0, const FftClass& c, const int32_t* rad,
                       const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
+  const int p = c.nrad;
   if (!c.bluestein) {
-    fft_lds<T, GRID_OUT ? OUT_GRID : OUT_PLAIN>(e0, c.L, c.nrad, rad, tw, nullptr, io, c.h, lt, nt);
+    fft_passes<T, GRID_OUT ? OUT_GRID : OUT_PLAIN>(e0, c.L, rad, 0, p, 1, tw, nullptr, io, c.h, lt, nt);
     return;
   }
-  fft_lds<T, OUT_KHAT>(e0, c.L, c.nrad, rad, tw, tabs + c.khat_off, nullptr, c.h, lt, nt);
-  fft_lds<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP>(e0, c.L, c.nrad, rad, tw, tabs + c.chirp_off, io, c.h, lt, nt);
+  const int R = gload(rad);
+  fft_passes<T, OUT_PLAIN>(e0, c.L, rad, 0, p - 1, 1, tw, nullptr, nullptr, c.h, lt, nt);
+  middle_dispatch<T>(R, e0, c.L, tw + (c.L / R - 1), tabs + c.khat_off, lt, nt);
+  fft_passes<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP>(e0, c.L, rad, 1, p, R, tw + (R - 1), tabs + c.chirp_off, io,
+                                                       c.h, lt, nt);
 }
 
 // Sweeps over a ring (gathers, scatters) issue the global loads of
