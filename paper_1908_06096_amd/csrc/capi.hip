@@ -234,42 +234,46 @@ void legendre_items_raw(const sht_plan_s* p, int variant, int plan, std::vector<
   }
 }
 
-// Work groups go to the XCDs round-robin by id.  Tiles that share an
-// operand slice (same plan, m and row tile t0: the synthesis table rows, or
-// the analysis table columns) are given ids congruent modulo NUM_XCD, 8 such
-// groups side by side, so that they run on one XCD at the same time and read
-// the slice through its L2 once.  Empty slots (m = -1) pad a group shorter
-// than the others of its eight.  Input: items of one group consecutive.
+// Work groups go to the XCDs round-robin by id.
 constexpr int NUM_XCD = 8;
 
-void legendre_arrange(std::vector<WorkItem>* items) {
+// A work list with every tile of a wavenumber on one XCD: each operand
+// slice of (plan, m) (table rows or columns, spectral or Fourier columns)
+// is shared by the tiles of the other dimension, and with all of them on
+// one XCD both slices come through its L2 once (spreading them over the
+// XCDs read the spectral and Fourier slices from memory once per tile of
+// the other dimension).  Wavenumbers go to the XCD with the least work so
+// far (items arrive costliest first; the work of an item is `steps(item)`),
+// and the XCD queues are interleaved by id, with empty slots (m = -1) where
+// a queue has run out.  Input: the items of one (plan, m) consecutive.
+template <typename Steps>
+void legendre_arrange(std::vector<WorkItem>* items, Steps steps) {
   std::vector<WorkItem> in;
   in.swap(*items);
+  std::vector<WorkItem> q[NUM_XCD];
+  double load[NUM_XCD] = {0};
   size_t i = 0;
   while (i < in.size()) {
-    size_t start[NUM_XCD], len[NUM_XCD], most = 0;
-    int ng = 0;
-    while (ng < NUM_XCD && i < in.size()) {
-      size_t j = i;
-      while (j < in.size() && in[j].plan == in[i].plan && in[j].m == in[i].m && in[j].t0 == in[i].t0) ++j;
-      start[ng] = i;
-      len[ng] = j - i;
-      most = std::max(most, len[ng]);
-      ++ng;
-      i = j;
-    }
-    for (size_t r = 0; r < most; ++r)
-      for (int g = 0; g < NUM_XCD; ++g)
-        items->push_back(g < ng && r < len[g] ? in[start[g] + r] : WorkItem{-1, 0, 0, 0});
+    size_t j = i;
+    while (j < in.size() && in[j].m == in[i].m && in[j].plan == in[i].plan) ++j;
+    const int x = (int)(std::min_element(load, load + NUM_XCD) - load);
+    load[x] += (double)(j - i) * steps(in[i]);
+    q[x].insert(q[x].end(), in.begin() + i, in.begin() + j);
+    i = j;
   }
+  size_t most = 0;
+  for (const auto& v : q) most = std::max(most, v.size());
+  for (size_t r = 0; r < most; ++r)
+    for (int x = 0; x < NUM_XCD; ++x) items->push_back(r < q[x].size() ? q[x][r] : WorkItem{-1, 0, 0, 0});
 }
 
 // Arranged work lists of one plan.
 void legendre_items(const sht_plan_s* p, int variant, int plan, std::vector<WorkItem>* inv,
                     std::vector<WorkItem>* dir) {
   legendre_items_raw(p, variant, plan, inv, dir);
-  legendre_arrange(inv);
-  legendre_arrange(dir);
+  // synthesis tiles step through k, analysis tiles through the rings
+  legendre_arrange(inv, [&](const WorkItem& w) { return (double)std::max(p->ms[w.m].Kp[0], p->ms[w.m].Kp[1]) + 8.0; });
+  legendre_arrange(dir, [&](const WorkItem& w) { return (double)p->ms[w.m].Lp + 8.0; });
 }
 
 // FFT work items (chunks of up to FFT_FCHUNK fields) of one plan, longest
@@ -710,8 +714,10 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
                      [&](const WorkItem& x, const WorkItem& y) { return inv_cost(b, x) > inv_cost(b, y); });
     std::stable_sort(b->dir[v].begin(), b->dir[v].end(),
                      [&](const WorkItem& x, const WorkItem& y) { return dir_cost(b, x) > dir_cost(b, y); });
-    legendre_arrange(&b->inv[v]);
-    legendre_arrange(&b->dir[v]);
+    legendre_arrange(&b->inv[v], [&](const WorkItem& w) { return (double)inv_cost(b, w) + 8.0; });
+    legendre_arrange(&b->dir[v], [&](const WorkItem& w) {
+      return (double)b->plans[w.plan]->ms[w.m].Lp + 8.0;
+    });
   }
   for (int t = 0; t < FFT_TIERS; ++t) {
     std::stable_sort(st[t].begin(), st[t].end(),
