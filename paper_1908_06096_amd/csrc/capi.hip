@@ -41,19 +41,21 @@ bool five_smooth(int64_t x) {
   return x == 1;
 }
 
-// A length the passes can factor: no prime factor above 23, the largest
-// prime radix.  (Primes up to 47 were measured: their butterflies need all
-// 128 registers of an FP32 pass, which makes the kernels around the passes
-// spill, and the FFT stages came out slower than with 23.)
-bool radix_smooth(int64_t x) {
+// A length the passes of a precision can factor: no prime factor above its
+// largest prime radix, 47 in FP32 (the primes above FFT_BIG_PRIME run in
+// kernels of their own) and FFT_BIG_PRIME in FP64 (where those butterflies
+// spill).
+bool radix_smooth(int64_t x, int prec) {
   if (x < 1) return false;
-  for (int p : {2, 3, 5, 7, 11, 13, 17, 19, 23})
-    while (x % p == 0) x /= p;
+  const int maxp = prec == SHT_FP64 ? FFT_BIG_PRIME : 47;
+  for (int p : {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47})
+    if (p <= maxp)
+      while (x % p == 0) x /= p;
   return x == 1;
 }
 
 // Radices the passes can use (each has a register butterfly), larger first.
-constexpr int kRadices[] = {23, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+constexpr int kRadices[] = {47, 43, 41, 37, 31, 29, 23, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
 
 // A pass of radix R over L points fits `threads` threads when its L / R
 // butterflies fit the FFT_REGS / R butterflies each thread holds (one for
@@ -81,7 +83,7 @@ int fewest_passes(int L, int x, int threads, std::map<int, std::pair<int, int>>*
   return bp;
 }
 
-// Radix sequence for a length without prime factors above 23 (the chirp-z
+// Radix sequence for a length without prime factors above 47 (the chirp-z
 // lengths are 5-smooth): the fewest passes that all fit
 // `threads` threads, the larger radix first among equally short sequences.
 // Each pass is one LDS round trip and two barriers, which is what the
@@ -195,8 +197,8 @@ struct sht_plan_s {
   std::vector<MInfo> ms;
   std::vector<int64_t> ring_off, four_row;
   std::vector<WorkItem> inv_items, dir_items;
-  std::vector<FftItem> syn_items, ana_items;  // tier-0 work groups first
-  int syn_split = 0, ana_split = 0;           // number of tier-0 work groups
+  std::vector<FftItem> syn_items, ana_items;  // work groups, tier by tier
+  int syn_off[FFT_TIERS + 1] = {}, ana_off[FFT_TIERS + 1] = {};  // first work group of each tier
   int64_t tab_plane = 0;
   size_t tab_bytes = 0, fft_bytes = 0;
   size_t lds_syn = 0, lds_ana = 0;            // largest of the tiers'
@@ -338,11 +340,14 @@ void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
 // per field.
 void choose_groups(int prec, std::vector<FftClass>* cls) {
   auto lds = [&](const FftClass& c, int G) { return fft_lds_bytes(prec, c.L, G); };
-  const int full = fft_blocks_per_cu(prec, 0, 0);
   for (FftClass& c : *cls) {
+    // a prime radix above FFT_BIG_PRIME is always the first pass
+    const int big = c.rad[0] > FFT_BIG_PRIME ? 2 : 0;
+    const int full = fft_blocks_per_cu(prec, big, 0);
     const std::vector<int> rs = radices(c.L, FFT_THREADS_SMALL, c.bluestein);
-    c.tier = (!rs.empty() && (int)rs.size() == c.nrad && fft_blocks_per_cu(prec, 0, lds(c, 1)) >= full) ? 0 : 1;
-    if (c.tier == 0)
+    const bool small = !rs.empty() && (int)rs.size() == c.nrad && fft_blocks_per_cu(prec, big, lds(c, 1)) >= full;
+    c.tier = big + (small ? 0 : 1);
+    if (small)
       for (size_t q = 0; q < rs.size(); ++q) c.rad[q] = rs[q];
   }
   size_t budget[FFT_TIERS];
@@ -376,12 +381,13 @@ void choose_groups(int prec, std::vector<FftClass>* cls) {
   }
 }
 
-// The two launches of an FFT stage over a work list whose first `split`
-// work groups belong to tier 0, one work group per list entry.
-hipError_t fft_launch_tiers(bool synthesis, const DevPlan* plans, int prec, const FftItem* items, int n, int split,
+// The launches of an FFT stage, one per tier, over a work list whose
+// work groups off[t] <= i < off[t + 1] belong to tier t, one work group per
+// list entry (a launch with none is skipped).
+hipError_t fft_launch_tiers(bool synthesis, const DevPlan* plans, int prec, const FftItem* items, const int* off,
                             const IoBind* io, IoBind io0, const size_t* lds, hipStream_t s) {
   for (int t = 0; t < FFT_TIERS; ++t) {
-    const int first = t ? split : 0, count = t ? n - split : split;
+    const int first = off[t], count = off[t + 1] - off[t];
     const hipError_t e =
         synthesis ? launch_fourier_synthesis(plans, prec, t, items + first, count, io, io0, lds[t],
                                              (int)fft_grid_blocks(count), s)
@@ -393,15 +399,16 @@ hipError_t fft_launch_tiers(bool synthesis, const DevPlan* plans, int prec, cons
 }
 
 // One launch list from per-tier chunk lists (each in launch order): each
-// tier's chunks become its work groups, tier 0 first.  Returns the number of
-// tier-0 work groups.
-int fft_join(const sht_plan_t* plans, std::vector<FftItem>* tiers, std::vector<FftItem>* out) {
+// tier's chunks become its work groups, tier by tier; off[t] is the first
+// work group of tier t, off[FFT_TIERS] the total.
+void fft_join(const sht_plan_t* plans, std::vector<FftItem>* tiers, std::vector<FftItem>* out, int* off) {
   out->clear();
-  for (int t = 0; t < FFT_TIERS; ++t) fft_arrange(plans, &tiers[t]);
-  out->insert(out->end(), tiers[0].begin(), tiers[0].end());
-  const int split = (int)out->size();
-  for (int t = 1; t < FFT_TIERS; ++t) out->insert(out->end(), tiers[t].begin(), tiers[t].end());
-  return split;
+  for (int t = 0; t < FFT_TIERS; ++t) {
+    fft_arrange(plans, &tiers[t]);
+    off[t] = (int)out->size();
+    out->insert(out->end(), tiers[t].begin(), tiers[t].end());
+  }
+  off[FFT_TIERS] = (int)out->size();
 }
 
 int build_host(sht_plan_s* p) {
@@ -446,7 +453,7 @@ int build_host(sht_plan_s* p) {
   for (int h : hs) {
     FftClass c{};
     c.h = h;
-    if (radix_smooth(h) && !radices(h).empty()) {
+    if (radix_smooth(h, p->prec) && !radices(h).empty()) {
       c.L = h;
       c.bluestein = 0;
     } else {
@@ -522,8 +529,8 @@ int build_host(sht_plan_s* p) {
   {
     std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
     fft_items(p, 0, st, at);
-    p->syn_split = fft_join(&p, st, &p->syn_items);
-    p->ana_split = fft_join(&p, at, &p->ana_items);
+    fft_join(&p, st, &p->syn_items, p->syn_off);
+    fft_join(&p, at, &p->ana_items, p->ana_off);
   }
   return SHT_OK;
 }
@@ -655,8 +662,8 @@ struct sht_batch_s {
   std::vector<sht_plan_t> plans;
   std::vector<int> variant;
   std::vector<WorkItem> inv[NUM_TILE_VARIANTS], dir[NUM_TILE_VARIANTS];
-  std::vector<FftItem> syn, ana;  // tier-0 work groups first
-  int syn_split = 0, ana_split = 0;
+  std::vector<FftItem> syn, ana;  // work groups, tier by tier
+  int syn_off[FFT_TIERS + 1] = {}, ana_off[FFT_TIERS + 1] = {};
   std::vector<size_t> ws_off;
   size_t ws_bytes = 0;
   size_t lds_syn = 0, lds_ana = 0;
@@ -725,8 +732,8 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
     std::stable_sort(at[t].begin(), at[t].end(),
                      [&](const FftItem& x, const FftItem& y) { return fft_cost(b, x) > fft_cost(b, y); });
   }
-  b->syn_split = fft_join(b->plans.data(), st, &b->syn);
-  b->ana_split = fft_join(b->plans.data(), at, &b->ana);
+  fft_join(b->plans.data(), st, &b->syn, b->syn_off);
+  fft_join(b->plans.data(), at, &b->ana, b->ana_off);
 
   destroy_graphs(b);
   if (b->arena) {
@@ -793,14 +800,14 @@ int batch_enqueue_inverse(sht_batch_s* b, hipStream_t s) {
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v)
     HIP_TRY(launch_legendre_inverse(b->d_plans, b->prec, v, b->d_inv[v], (int)b->inv[v].size(), b->d_io, none,
                                     b->grid_inv[v], s));
-  HIP_TRY(fft_launch_tiers(true, b->d_plans, b->prec, b->d_syn, (int)b->syn.size(), b->syn_split, b->d_io, none,
+  HIP_TRY(fft_launch_tiers(true, b->d_plans, b->prec, b->d_syn, b->syn_off, b->d_io, none,
                            b->lds_syn_t, s));
   return SHT_OK;
 }
 
 int batch_enqueue_direct(sht_batch_s* b, hipStream_t s) {
   const IoBind none{};
-  HIP_TRY(fft_launch_tiers(false, b->d_plans, b->prec, b->d_ana, (int)b->ana.size(), b->ana_split, b->d_io, none,
+  HIP_TRY(fft_launch_tiers(false, b->d_plans, b->prec, b->d_ana, b->ana_off, b->d_io, none,
                            b->lds_ana_t, s));
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v)
     HIP_TRY(launch_legendre_direct(b->d_plans, b->prec, v, b->d_dir[v], (int)b->dir[v].size(), b->d_io, none,
@@ -910,8 +917,8 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   {
     std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
     fft_items(p, 0, st, at);
-    p->syn_split = fft_join(&p, st, &p->syn_items);
-    p->ana_split = fft_join(&p, at, &p->ana_items);
+    fft_join(&p, st, &p->syn_items, p->syn_off);
+    fft_join(&p, at, &p->ana_items, p->ana_off);
   }
   int rc = build_own(p, (hipStream_t)hip_stream);
   if (rc == SHT_OK) {
@@ -1017,14 +1024,14 @@ int sht_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* strea
 
 int sht_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream) {
   if (!p || !four || !grid) return SHT_EINVAL;
-  HIP_TRY(fft_launch_tiers(true, p->d_self, p->prec, p->d_syn, (int)p->syn_items.size(), p->syn_split, nullptr,
+  HIP_TRY(fft_launch_tiers(true, p->d_self, p->prec, p->d_syn, p->syn_off, nullptr,
                            bind_of(nullptr, grid, four), p->lds_syn_t, (hipStream_t)stream));
   return SHT_OK;
 }
 
 int sht_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* stream) {
   if (!p || !four || !grid) return SHT_EINVAL;
-  HIP_TRY(fft_launch_tiers(false, p->d_self, p->prec, p->d_ana, (int)p->ana_items.size(), p->ana_split, nullptr,
+  HIP_TRY(fft_launch_tiers(false, p->d_self, p->prec, p->d_ana, p->ana_off, nullptr,
                            bind_of(nullptr, grid, four), p->lds_ana_t, (hipStream_t)stream));
   return SHT_OK;
 }

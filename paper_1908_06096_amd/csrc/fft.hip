@@ -4,8 +4,8 @@
 //
 // A ring of n = 2h points is transformed as a complex DFT of length h of
 // z_t = g_{2t} + i g_{2t+1} plus an O(h) pre/post step.  The complex DFT is
-// an in-LDS Stockham autosort FFT when h has no prime factor above 23 (the
-// largest prime radix); otherwise it is the chirp-z (Bluestein) identity
+// an in-LDS Stockham autosort FFT when h has no prime factor above the
+// largest prime radix (47 in FP32, 23 in FP64); otherwise it is the chirp-z (Bluestein) identity
 //   X_q = c_q sum_t (z_t c_t) conj(c_{q-t}),  c_t = exp(-i pi t^2 / h),
 // evaluated as a cyclic convolution of 5-smooth length L >= 2h - 1 with two
 // more FFTs.  Inverse DFTs use conj(DFT(conj(x))).
@@ -232,12 +232,13 @@ __device__ inline void butterfly_odd(typename V2T<T>::type* v) {
 }
 
 __host__ __device__ constexpr bool odd_prime_radix(int R) {
-  return R == 7 || R == 11 || R == 13 || R == 17 || R == 19 || R == 23;
+  return R == 7 || R == 11 || R == 13 || R == 17 || R == 19 || R == 23 || R == 29 || R == 31 || R == 37 ||
+         R == 41 || R == 43 || R == 47;
 }
 
 // Forward DFT of R points in registers.  Radices 2, 3, 4 and 5 are written
 // out; 8 and 16 take one even/odd step, 9 a 3 x 3 step, the odd primes
-// from 7 to 23 the pair form above, and the composite radices 6, 10, 12,
+// from 7 to 47 the pair form above, and the composite radices 6, 10, 12,
 // 14, 15, 18 and 20 the generic step above.
 template <typename T, int R>
 __device__ inline void butterfly(typename V2T<T>::type* v) {
@@ -434,13 +435,25 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
   __syncthreads();
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool BIG>
 __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
                                      const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                      typename V2T<T>::type* io, int h, int lt, int nt) {
 #define SHT_PASS(RR) stockham_pass<T, RR, MODE>(e0, L, Ns, tw, aux, io, h, lt, nt)
   // radices with a factor above 5 occur only in plain transforms of length h
-  // (the chirp-z lengths are 5-smooth)
+  // (the chirp-z lengths are 5-smooth); the primes above FFT_BIG_PRIME only
+  // in the BIG kernels, and only in FP32
+  if constexpr ((MODE == OUT_PLAIN || MODE == OUT_GRID) && BIG && sizeof(T) == 4) {
+    switch (R) {
+      case 47: SHT_PASS(47); return;
+      case 43: SHT_PASS(43); return;
+      case 41: SHT_PASS(41); return;
+      case 37: SHT_PASS(37); return;
+      case 31: SHT_PASS(31); return;
+      case 29: SHT_PASS(29); return;
+      default: break;
+    }
+  }
   if constexpr (MODE == OUT_PLAIN || MODE == OUT_GRID) {
     switch (R) {
       case 23: SHT_PASS(23); return;
@@ -475,14 +488,14 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
 // after Ns points have been combined with tw at pass q0's table; the last of
 // them applies MODE with aux and io.  All passes from Ns = 1: natural order
 // in and out.
-template <typename T, int MODE>
+template <typename T, int MODE, bool BIG>
 __device__ __forceinline__ void fft_passes(uint32_t e0, int L, const int32_t* rad, int q0, int q1, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                            typename V2T<T>::type* io, int h, int lt, int nt) {
   for (int q = q0; q < q1; ++q) {
     const int R = gload(rad + q);
-    if (q == q1 - 1) pass_dispatch<T, MODE>(R, e0, L, Ns, tw, aux, io, h, lt, nt);
-    else pass_dispatch<T, OUT_PLAIN>(R, e0, L, Ns, tw, nullptr, nullptr, h, lt, nt);
+    if (q == q1 - 1) pass_dispatch<T, MODE, BIG>(R, e0, L, Ns, tw, aux, io, h, lt, nt);
+    else pass_dispatch<T, OUT_PLAIN, BIG>(R, e0, L, Ns, tw, nullptr, nullptr, h, lt, nt);
     tw += Ns * (R - 1);
     Ns *= R;
   }
@@ -567,20 +580,20 @@ __device__ __forceinline__ void middle_dispatch(int R, uint32_t e0, int L, const
 // same radix, so the second DFT's first pass fuses with the first DFT's
 // last (a chirp-z length exceeds the largest radix, so each DFT has at
 // least two passes).
-template <typename T, bool GRID_OUT>
+template <typename T, bool GRID_OUT, bool BIG>
 __device__ __forceinline__ void dft_h(uint32_t e0, const FftClass& c, const int32_t* rad,
                       const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
   const int p = c.nrad;
   if (!c.bluestein) {
-    fft_passes<T, GRID_OUT ? OUT_GRID : OUT_PLAIN>(e0, c.L, rad, 0, p, 1, tw, nullptr, io, c.h, lt, nt);
+    fft_passes<T, GRID_OUT ? OUT_GRID : OUT_PLAIN, BIG>(e0, c.L, rad, 0, p, 1, tw, nullptr, io, c.h, lt, nt);
     return;
   }
   const int R = gload(rad);
-  fft_passes<T, OUT_PLAIN>(e0, c.L, rad, 0, p - 1, 1, tw, nullptr, nullptr, c.h, lt, nt);
+  fft_passes<T, OUT_PLAIN, false>(e0, c.L, rad, 0, p - 1, 1, tw, nullptr, nullptr, c.h, lt, nt);
   middle_dispatch<T>(R, e0, c.L, tw + (c.L / R - 1), tabs + c.khat_off, lt, nt);
-  fft_passes<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP>(e0, c.L, rad, 1, p, R, tw + (R - 1), tabs + c.chirp_off, io,
-                                                       c.h, lt, nt);
+  fft_passes<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP, false>(e0, c.L, rad, 1, p, R, tw + (R - 1),
+                                                              tabs + c.chirp_off, io, c.h, lt, nt);
 }
 
 // Sweeps over a ring (gathers, scatters) issue the global loads of
@@ -601,7 +614,7 @@ size_t fft_grid_blocks(int nitems) { return (size_t)nitems; }
 // neighbouring lanes read neighbouring fields of one Fourier row.
 // ---------------------------------------------------------------------------
 
-template <typename T, int NT>
+template <typename T, int NT, bool BIG>
 __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int fb, int fend,
                                                 const T* __restrict__ four, T* __restrict__ grid) {
   typedef typename V2T<T>::type C;
@@ -681,7 +694,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
     const int f = fb + sub;
     C* g = f < fend ? (C*)(grid + (int64_t)f * p.npts + ri.goff) : nullptr;
     // the last pass writes the grid (the conjugate of the inverse transform)
-    dft_h<T, true>(sub * fs, cl, rad, tabs, g, lt, nt);
+    dft_h<T, true, BIG>(sub * fs, cl, rad, tabs, g, lt, nt);
   }
 }
 
@@ -698,7 +711,7 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
 //   neighbouring fields of one Fourier row.
 // ---------------------------------------------------------------------------
 
-template <typename T, int NT>
+template <typename T, int NT, bool BIG>
 __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int fb, int fend,
                                                const T* __restrict__ grid, T* __restrict__ four) {
   typedef typename V2T<T>::type C;
@@ -739,7 +752,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
       }
     }
     __syncthreads();
-    dft_h<T, false>(dst, cl, rad, tabs, nullptr, lt, nt);
+    dft_h<T, false, BIG>(dst, cl, rad, tabs, nullptr, lt, nt);
     const int nm = M << gs;
     for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * NT) {
       C pm[FFT_SWEEP];
@@ -784,7 +797,7 @@ struct FftWaves {
   static constexpr int value = sizeof(T) == 4 ? 4 : 2;
 };
 
-template <typename T, int NT>
+template <typename T, int NT, bool BIG>
 __global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_synthesis_kernel(const DevPlan* __restrict__ plans,
                                                                                   const FftItem* __restrict__ items,
                                                                                   int nitems,
@@ -795,11 +808,11 @@ __global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_synthesis_kern
     if (it.ring < 0) continue;
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    synthesis_group<T, NT>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid);
+    synthesis_group<T, NT, BIG>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid);
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, bool BIG>
 __global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_analysis_kernel(const DevPlan* __restrict__ plans,
                                                                                  const FftItem* __restrict__ items,
                                                                                  int nitems,
@@ -810,24 +823,25 @@ __global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_analysis_kerne
     if (it.ring < 0) continue;
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    analysis_group<T, NT>(p, it.ring, it.f0, it.fend, (const T*)b.grid, (T*)b.ws);
+    analysis_group<T, NT, BIG>(p, it.ring, it.f0, it.fend, (const T*)b.grid, (T*)b.ws);
   }
 }
 
-// The kernel of a precision, direction and tier.
+// The kernel of a precision, direction and tier (FP64 classes never take
+// the prime radices above FFT_BIG_PRIME, so its tiers 2 and 3 are 0 and 1).
+template <typename T, bool BIG>
+static const void* fft_kernel_of(bool synthesis, bool large) {
+  if (synthesis)
+    return large ? (const void*)fourier_synthesis_kernel<T, FFT_THREADS, BIG>
+                 : (const void*)fourier_synthesis_kernel<T, FFT_THREADS_SMALL, BIG>;
+  return large ? (const void*)fourier_analysis_kernel<T, FFT_THREADS, BIG>
+               : (const void*)fourier_analysis_kernel<T, FFT_THREADS_SMALL, BIG>;
+}
+
 static const void* fft_kernel(int prec, bool synthesis, int tier) {
-  if (synthesis) {
-    if (prec == SHT_FP64)
-      return tier ? (const void*)fourier_synthesis_kernel<double, FFT_THREADS>
-                  : (const void*)fourier_synthesis_kernel<double, FFT_THREADS_SMALL>;
-    return tier ? (const void*)fourier_synthesis_kernel<float, FFT_THREADS>
-                : (const void*)fourier_synthesis_kernel<float, FFT_THREADS_SMALL>;
-  }
-  if (prec == SHT_FP64)
-    return tier ? (const void*)fourier_analysis_kernel<double, FFT_THREADS>
-                : (const void*)fourier_analysis_kernel<double, FFT_THREADS_SMALL>;
-  return tier ? (const void*)fourier_analysis_kernel<float, FFT_THREADS>
-              : (const void*)fourier_analysis_kernel<float, FFT_THREADS_SMALL>;
+  const bool large = (tier & 1) != 0;
+  if (prec == SHT_FP64) return fft_kernel_of<double, false>(synthesis, large);
+  return tier >= 2 ? fft_kernel_of<float, true>(synthesis, large) : fft_kernel_of<float, false>(synthesis, large);
 }
 
 static hipError_t launch_fft(const void* f, int threads, int grid_blocks, size_t lds, hipStream_t s,

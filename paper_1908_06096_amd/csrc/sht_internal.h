@@ -28,15 +28,20 @@ constexpr int FPAD = 16;
 // FFT: threads per work group and complex values each thread may hold in
 // registers during one pass (or one butterfly of a prime radix above it);
 // together they bound the transform length.
-// Transforms run in work groups of FFT_THREADS_SMALL threads (tier 0) where
-// that many threads per field cover every pass with the fewest passes, else
-// of FFT_THREADS (tier 1): smaller groups wait at smaller barriers and more
-// of them share a CU.  A work group transforms up to G fields of one ring
-// side by side; work is listed in chunks of FFT_FCHUNK fields.
+// Transforms run in work groups of FFT_THREADS_SMALL threads (even tiers)
+// where that many threads per field cover every pass with the fewest
+// passes, else of FFT_THREADS (odd tiers): smaller groups wait at smaller
+// barriers and more of them share a CU.  Tiers 2 and 3 are the kernels that
+// also hold the passes of the prime radices above FFT_BIG_PRIME, for the
+// classes that need them (those butterflies take every register a pass has,
+// and in the other kernels they would make the code around the passes
+// spill).  A work group transforms up to G fields of one ring side by side;
+// work is listed in chunks of FFT_FCHUNK fields.
 constexpr int FFT_THREADS = 512;
 constexpr int FFT_THREADS_SMALL = 256;
-constexpr int FFT_TIERS = 2;
-__host__ __device__ constexpr int fft_tier_threads(int tier) { return tier ? FFT_THREADS : FFT_THREADS_SMALL; }
+constexpr int FFT_TIERS = 4;
+constexpr int FFT_BIG_PRIME = 23;
+__host__ __device__ constexpr int fft_tier_threads(int tier) { return (tier & 1) ? FFT_THREADS : FFT_THREADS_SMALL; }
 constexpr int FFT_REGS = 20;
 constexpr int FFT_MAX_RADICES = 20;
 constexpr int FFT_FCHUNK = 16;
@@ -123,8 +128,9 @@ struct RingInfo {
 
 // One FFT class per distinct half length h = nlon / 2.  The real DFT of
 // length 2h is carried out as a complex DFT of length h; when h has a prime
-// factor above 23 (the largest prime radix) that DFT is a chirp-z
-// convolution of length L (5-smooth, L >= 2h - 1), otherwise L = h.
+// factor above the largest prime radix (47 in FP32, 23 in FP64) that DFT is
+// a chirp-z convolution of length L (5-smooth, L >= 2h - 1), otherwise
+// L = h.
 struct FftClass {
   int32_t h;
   int32_t L;
@@ -133,7 +139,8 @@ struct FftClass {
   int32_t rad[FFT_MAX_RADICES];
   int32_t G;          // fields transformed side by side per work group (power of two)
   int32_t gshift;     // log2 G; each field gets fft_tier_threads(tier) / G threads
-  int32_t tier;       // work-group size: fft_tier_threads(tier)
+  int32_t tier;       // launch: work-group size fft_tier_threads(tier), prime radices above
+                      // FFT_BIG_PRIME when tier >= 2
   int64_t root_off;   // L - 1 twiddles, pass after pass: exp(-2 pi i r k / (Ns R)) at
                       // k (R - 1) + r - 1 of the pass table (k < Ns, 1 <= r < R)
   int64_t post_off;   // h complex values exp(-2 pi i q / (2h))

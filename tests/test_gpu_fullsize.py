@@ -62,14 +62,14 @@ def _largest_prime(x):
 
 def _rings(geo):
     """Poles, equator, a ring in between, and on octahedral grids the longest
-    southern-hemisphere rings whose half length's largest prime factor is 7,
-    11, 13, 17, 19 and 23 (transforms whose passes take those prime
-    radices)."""
+    southern-hemisphere rings whose half length's largest prime factor is
+    each prime from 7 to 47 (FP32 transforms whose passes take those prime
+    radices; in FP64 the ones above 23 are chirp-z convolutions)."""
     nlat = geo["nlat"]
     nh = nlat // 2
     rings = {0, 1, nlat // 5, nh - 1, nh, nlat - 2, nlat - 1}
     if geo["grid"] == "octahedral":
-        want = {7, 11, 13, 17, 19, 23}
+        want = {7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47}
         for j in range(nh, nlat):
             p = _largest_prime(int(geo["nlon"][j]) // 2)
             if p in want:
