@@ -329,10 +329,12 @@ void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
   }
 }
 
-// Work-group size and fields per work group of each FFT class.  Tier 0 (FFT_THREADS_SMALL threads) where that many threads
-// per field reach the pass count FFT_THREADS threads do, and one field's LDS
-// leaves the small groups' occupancy at what their registers allow (a
-// launch's LDS per group is its largest item's).  G: the most fields (up to
+// Work-group size and fields per work group of each FFT class.  An even
+// tier (FFT_THREADS_SMALL threads) where that many threads per field reach
+// the pass count FFT_THREADS threads do, and one field's LDS leaves the small
+// groups' occupancy at what their registers allow (a launch's LDS per group
+// is its largest item's); tiers 2 and 3 for the classes whose first radix is
+// a prime above FFT_BIG_PRIME.  G: the most fields (up to
 // FFT_MAX_G) whose threads per field (the tier's work-group size / G) still
 // hold every pass with the same pass count and whose LDS fits the tier's
 // budget, the most LDS that keeps the occupancy the tier's longest class has
