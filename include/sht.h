@@ -217,8 +217,9 @@ int sht_plan_set_tile(sht_plan_t plan, int tile, void* hip_stream);
 
 /* Batches: many independent transforms of uneven truncation and field count
  * run in shared launches -- one launch per stage (per tile variant present
- * for the Legendre products) over the concatenation of every plan's work
- * list, ordered by cost, largest first.  This is the report's batching of
+ * for the Legendre products, per work-group kind present for the FFTs) over
+ * the concatenation of every plan's work list, ordered by cost, largest
+ * first.  This is the report's batching of
  * the Legendre products across the second spherical dimension (section
  * 4.2.4) taken one step further: across transforms, with each product at
  * its own size instead of zero-padding to a common one, and its wish for an
