@@ -637,20 +637,19 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
     // X_{h-q}, so pair p = q (0 <= q <= h/2) loads them once and writes both
     const int np = (h / 2 + 1) << gs;
     for (int e0 = threadIdx.x; e0 < np; e0 += FFT_SWEEP * NT) {
-      C xa[FFT_SWEEP], xb[FFT_SWEEP], pa[FFT_SWEEP], pb[FFT_SWEEP], ca[FFT_SWEEP], cb[FFT_SWEEP];
+      // the factors of h - q follow from those of q: w^{-(h-q)} = -conj(w^{-q})
+      // and c_{h-q} = (-1)^h c_q ((h - q)^2 = q^2 mod 2h for even h)
+      C xa[FFT_SWEEP], xb[FFT_SWEEP], pa[FFT_SWEEP], ca[FFT_SWEEP];
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int e = e0 + u * NT;
         const int s = e & (G - 1), q = e >> gs, q2 = h - q;
         const bool ok = e < np && fb + s < fend;
-        const bool two = ok && q >= 1 && q2 != q;  // q2 < h is a distinct index
         const C* cf = fc + ri.frow * Fp + fb + s;
         xa[u] = (ok && q <= mmax) ? gload(cf + q * Fp) : C{0, 0};
         xb[u] = (ok && q >= 1 && q2 <= mmax) ? gload(cf + q2 * Fp) : C{0, 0};
         pa[u] = ok ? gload(post + q) : C{1, 0};
-        pb[u] = two ? gload(post + q2) : C{1, 0};
         ca[u] = (ok && blue) ? gload(chirp + q) : C{1, 0};
-        cb[u] = (two && blue) ? gload(chirp + q2) : C{1, 0};
       }
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
@@ -670,12 +669,12 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
             lds_store(lds_elem<C>(s * fs + q), y);
           }
           if (q >= 1 && q2 != q) {
-            // Z_{h-q} from X_{h-q} = B and conj X_q = conj A
+            // Z_{h-q} from X_{h-q} = B and conj X_q = conj A; conj(w^{-(h-q)}) = -w^{-q}
             const C xr = cconj(A);
             const C sm = cadd(B, xr);
-            const C t = cmul(cconj(pb[u]), csub(B, xr));
+            const C t = cmul(pa[u], csub(xr, B));
             C y = C{sm.x - t.y, -(sm.y + t.x)};
-            if (blue) y = cmul(y, cb[u]);
+            if (blue) y = cmul(y, (h & 1) ? C{-ca[u].x, -ca[u].y} : ca[u]);
             lds_store(lds_elem<C>(s * fs + q2), y);
           }
         }
