@@ -352,7 +352,7 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
 }
 
 // What the last pass of a transform does with its outputs.
-enum PassOut { OUT_PLAIN = 0, OUT_CHIRP = 1, OUT_GRID = 2, OUT_GRID_CHIRP = 3 };
+enum PassOut { OUT_PLAIN = 0, OUT_HEAD = 1, OUT_GRID = 2, OUT_GRID_CHIRP = 3 };
 
 // One Stockham pass of radix R over L points in LDS, after Ns points have
 // been combined, carried out by the nt threads (thread lt) that own this
@@ -361,11 +361,12 @@ enum PassOut { OUT_PLAIN = 0, OUT_CHIRP = 1, OUT_GRID = 2, OUT_GRID_CHIRP = 3 };
 // (b mod Ns)(R - 1) + r - 1, so lanes with consecutive b read consecutive
 // entries) and writes y[(b / Ns) Ns R + b mod Ns + r Ns].  All reads of the
 // pass land in registers before the barrier, so one LDS buffer suffices.
-//   OUT_CHIRP stores c_q conj(y_q) for q < h (the last element-wise step
-//     of the chirp-z convolution);
+//   OUT_HEAD stores y_q for q < h only (the analysis applies the chirp-z
+//     convolution's last element-wise step, c_q conj(y_q), to the values it
+//     reads afterwards);
 //   OUT_GRID writes conj(y_q) and OUT_GRID_CHIRP writes conj(c_q) y_q, the
-//     conjugate of what OUT_PLAIN and OUT_CHIRP would store, for q < h to
-//     io in device memory (nothing when io is null).
+//     conjugates of y_q and of c_q conj(y_q), for q < h to io in device
+//     memory (nothing when io is null).
 // Each instantiation is its own non-inlined function so that its registers
 // are allocated for it alone.  Every thread of the work group calls it (the
 // barriers).
@@ -415,8 +416,8 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
         const uint32_t ao = (uint32_t)o * (uint32_t)sizeof(C);
         if constexpr (MODE == OUT_PLAIN) {
           lds_store(lds_elem<C>(e0 + (uint32_t)o), y);
-        } else if constexpr (MODE == OUT_CHIRP) {
-          if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), cmul(buffer_load<C>(ars, ao), cconj(y)));
+        } else if constexpr (MODE == OUT_HEAD) {
+          if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), y);
         } else if constexpr (MODE == OUT_GRID) {
           if (io && o < h) gstore(io + o, cconj(y));
         } else {
@@ -574,9 +575,10 @@ __device__ __forceinline__ void middle_dispatch(int R, uint32_t e0, int L, const
 // Forward complex DFT of length h.  Input: z_t, t < h, in LDS at
 // element e0 + t, multiplied by the chirp c_t for chirp-z classes, whose
 // entries h <= t < L must be zero.  Output: Z_q, q < h, in LDS at element
-// e0 + q, or with GRID_OUT its conjugate written to io (nothing
-// when io is null).  Chirp-z: A = DFT_L(a), B = conj(A khat),
-// Z_q = c_q conj(DFT_L(B))_q.  The radix sequence begins and ends with the
+// e0 + q, or with GRID_OUT its conjugate written to io (nothing when io is
+// null).  Chirp-z: A = DFT_L(a), B = conj(A khat), y = DFT_L(B) and
+// Z_q = c_q conj(y_q); without GRID_OUT the LDS holds y_q, and the caller
+// forms Z_q for the q it reads.  The radix sequence begins and ends with the
 // same radix, so the second DFT's first pass fuses with the first DFT's
 // last (a chirp-z length exceeds the largest radix, so each DFT has at
 // least two passes).
@@ -592,8 +594,8 @@ __device__ __forceinline__ void dft_h(uint32_t e0, const FftClass& c, const int3
   const int R = gload(rad);
   fft_passes<T, OUT_PLAIN, false>(e0, c.L, rad, 0, p - 1, 1, tw, nullptr, nullptr, c.h, lt, nt);
   middle_dispatch<T>(R, e0, c.L, tw + (c.L / R - 1), tabs + c.khat_off, lt, nt);
-  fft_passes<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_CHIRP, false>(e0, c.L, rad, 1, p, R, tw + (R - 1),
-                                                              tabs + c.chirp_off, io, c.h, lt, nt);
+  fft_passes<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_HEAD, false>(e0, c.L, rad, 1, p, R, tw + (R - 1),
+                                                             tabs + c.chirp_off, io, c.h, lt, nt);
 }
 
 // Sweeps over a ring (gathers, scatters) issue the global loads of
@@ -752,13 +754,16 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
     }
     __syncthreads();
     dft_h<T, false, BIG>(dst, cl, rad, tabs, nullptr, lt, nt);
+    // chirp-z classes hold y_q: Z_m = c_m conj(y_m), and
+    // conj Z_{h-m} = conj(c_{h-m}) y_{h-m} with c_{h-m} = (-1)^h c_m
     const int nm = M << gs;
     for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * NT) {
-      C pm[FFT_SWEEP];
+      C pm[FFT_SWEEP], cm[FFT_SWEEP];
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int e = e0 + u * NT;
         pm[u] = e < nm ? gload(post + (e >> gs)) : C{0, 0};
+        cm[u] = (e < nm && blue) ? gload(chirp + (e >> gs)) : C{1, 0};
       }
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
@@ -766,8 +771,15 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
         if (e >= nm) continue;
         const int s = e & (G - 1), m = e >> gs;
         if (fb + s >= fend) continue;
-        const C zm = lds_load(lds_elem<C>(s * fs + m));
-        const C zr = cconj(lds_load(lds_elem<C>(s * fs + (m == 0 ? 0 : h - m))));
+        C zm = lds_load(lds_elem<C>(s * fs + m));
+        C zr = lds_load(lds_elem<C>(s * fs + (m == 0 ? 0 : h - m)));
+        if (blue) {
+          const C cr = (m > 0 && (h & 1)) ? C{-cm[u].x, -cm[u].y} : cm[u];
+          zm = cmul(cm[u], cconj(zm));
+          zr = cmul(cconj(cr), zr);
+        } else {
+          zr = cconj(zr);
+        }
         const C sm = cadd(zm, zr);
         const C d = csub(zm, zr);
         const C t = cmul(pm[u], d);
