@@ -284,6 +284,15 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
   static_assert((XUNITS % 256 == 0 || XUNITS < 256) && TUNITS % 256 == 0 && KJ % 4 == 0, "tile shape");
   __shared__ T Xs[2][KJ][BC + LDS_PAD];
   __shared__ T Ts[2][KJ][BK + LDS_PAD];
+  // FP32: in the table rows of rings 2 and 3 mod 4 the 16-byte column units
+  // swap in pairs (unit ^ 1).  Rows are 16 banks apart, so without it the
+  // staging writes (lanes of consecutive rings, one unit each) of rings r
+  // and r + 2 meet on the same banks; with it four consecutive rings use
+  // four bank groups.  The operand reads (rings 4s + lane / 16) take a
+  // permutation that is the same for a lane across the whole step and stays
+  // within 16-column blocks, so they remain conflict-free.
+  constexpr bool TSWZ = sizeof(T) == 4;
+  auto tcol = [](int ring, int col) { return TSWZ ? col ^ (VN * ((ring >> 1) & 1)) : col; };
 
   const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
@@ -371,7 +380,8 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
 #pragma unroll
     for (int a = 0; a < TU; ++a)
 #pragma unroll
-      for (int v = 0; v < KCH / VN; ++v) *(V*)&Ts[t_par[a]][t_rr[a]][t_ch[a] * KCH + v * VN] = rt[a][v];
+      for (int v = 0; v < KCH / VN; ++v)
+        *(V*)&Ts[t_par[a]][t_rr[a]][tcol(t_rr[a], t_ch[a] * KCH + v * VN)] = rt[a][v];
     __syncthreads();
     if (jc + 1 < nj) {
 #pragma unroll
@@ -387,7 +397,10 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
 #pragma unroll
         for (int i = 0; i < IC; ++i) av[i] = Xs[par][ks * 4 + (lane >> 4)][wr * WC + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < IK; ++j) bv[j] = Ts[par][ks * 4 + (lane >> 4)][wc * WK + j * 16 + (lane & 15)];
+        for (int j = 0; j < IK; ++j) {
+          const int ring = ks * 4 + (lane >> 4);
+          bv[j] = Ts[par][ring][tcol(ring, wc * WK + j * 16 + (lane & 15))];
+        }
 #pragma unroll
         for (int i = 0; i < IC; ++i)
 #pragma unroll
