@@ -124,6 +124,14 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
   static_assert(AUNITS % 256 == 0 && 256 % FT == 0 && (2 * KI) % TPF == 0 && TPF % 2 == 0, "tile shape");
   __shared__ T As[2][KI][BM + LDS_PAD];
   __shared__ T Bs[2][KI][BN + LDS_PAD];
+  // FP32: spectral row k of parity p has its column index XORed with
+  // 4 (2 p + (k / 2) mod 2).  The parities' planes and every other row share
+  // banks, so the staging writes (lanes of two fields over 8 (parity, k)
+  // pairs) would meet on 4 bank groups; permuted they use all 16.  The
+  // permutation stays within 16-column blocks and is the same for a lane
+  // across the step's operand reads, which stay conflict-free.
+  constexpr bool BSWZ = sizeof(T) == 4;
+  auto bcol = [](int par, int k, int col) { return BSWZ ? col ^ (4 * (2 * par + ((k >> 1) & 1))) : col; };
 
   const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
@@ -203,11 +211,12 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int k = (q >> 1) + (TPF / 2) * j;
-      *(C2*)&Bs[b_par][k][2 * fi] = rb[j];
+      const int bc = bcol(b_par, k, 2 * fi);
+      *(C2*)&Bs[b_par][k][bc] = rb[j];
       // Im a_n^0 is dropped: a constant store, so that nothing is computed
       // from the prefetched registers before this step (the compiler would
       // compute it right after the loads and wait for them there)
-      if (m0) Bs[b_par][k][2 * fi + 1] = 0;
+      if (m0) Bs[b_par][k][bc + 1] = 0;
     }
     __syncthreads();
     if (kc + 1 < nk) fetch(kc + 1);
@@ -219,7 +228,10 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
 #pragma unroll
         for (int i = 0; i < IM; ++i) av[i] = As[par][ks * 4 + (lane >> 4)][wr * WM + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < IN; ++j) bv[j] = Bs[par][ks * 4 + (lane >> 4)][wc * WN + j * 16 + (lane & 15)];
+        for (int j = 0; j < IN; ++j) {
+          const int k = ks * 4 + (lane >> 4);
+          bv[j] = Bs[par][k][bcol(par, k, wc * WN + j * 16 + (lane & 15))];
+        }
 #pragma unroll
         for (int i = 0; i < IM; ++i)
 #pragma unroll
