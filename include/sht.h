@@ -235,10 +235,15 @@ int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags
 size_t sht_batch_workspace_size(sht_batch_t batch);
 
 /* Bind the device buffers of every transform: spec[i] and grid[i] in plan
- * i's layouts, one workspace of sht_batch_workspace_size bytes.  Copies a
- * small descriptor table to the device (synchronous).  Rebinding is allowed
- * between runs; a captured graph reads the table, so it stays valid. */
-int sht_batch_bind(sht_batch_t batch, void* const* spec, void* const* grid, void* workspace);
+ * i's layouts, one workspace of sht_batch_workspace_size bytes.  The small
+ * device descriptor table is rewritten by a kernel enqueued on `hip_stream`,
+ * so the new binding takes effect in stream order: runs enqueued on that
+ * stream before the call keep the buffers they were bound to, runs after it
+ * use the new ones (no host synchronisation).  Runs on other streams must
+ * be ordered by the caller.  A captured graph reads the table, so it stays
+ * valid across rebinding. */
+int sht_batch_bind(sht_batch_t batch, void* const* spec, void* const* grid, void* workspace,
+                   void* hip_stream);
 
 /* Synthesis / analysis of every transform of the batch on `hip_stream`
  * (asynchronous).  SHT_EINVAL before the first sht_batch_bind. */

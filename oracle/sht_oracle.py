@@ -45,8 +45,13 @@ Parity status of each function:
 * ``dft_synthesis`` / ``dft_analysis`` pinned (library real FFT);
 * ``inverse`` / ``direct`` pinned (library spherical harmonics, single
   harmonic, Parseval, round trip);
-* ``grid_geometry`` -- the per-ring truncation rule is a reading with no
-  independent source: parity unpinned for that rule only.
+* ``grid_geometry`` pinned for the ring counts and lengths (the stated
+  TCo1279 shape: 2560 rings, 20 + 4i points, 5136 at the equator, 6,599,680
+  points; the 80 x 160 and 400 x 800 full grids) and the offsets; the
+  per-ring truncation rule is a reading with no independent source: parity
+  unpinned for that rule only;
+* ``spec_index`` / ``nspec_of`` pinned (a counter over the m-major
+  enumeration, the stated coefficient counts).
 """
 
 import math

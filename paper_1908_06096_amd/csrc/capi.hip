@@ -701,6 +701,32 @@ int64_t fft_cost(const sht_batch_s* b, const FftItem& w) {
   return (int64_t)p->classes[p->rings[w.ring].cls].L;
 }
 
+// The bound buffers reach the device table through kernel arguments: the
+// write is ordered on the caller's stream after the runs enqueued before
+// it (a run still in flight keeps the buffers it started with), and no host
+// staging buffer has to outlive the call.
+constexpr int BIND_CHUNK = 32;
+struct BindChunk {
+  IoBind io[BIND_CHUNK];
+};
+
+__global__ void write_binds_kernel(IoBind* dst, BindChunk c, int n) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = c.io[i];
+}
+
+hipError_t write_binds(IoBind* dst, const std::vector<IoBind>& io, hipStream_t s) {
+  for (size_t i0 = 0; i0 < io.size(); i0 += BIND_CHUNK) {
+    BindChunk c{};
+    const int n = (int)std::min<size_t>(BIND_CHUNK, io.size() - i0);
+    for (int k = 0; k < n; ++k) c.io[k] = io[i0 + k];
+    hipLaunchKernelGGL(write_binds_kernel, dim3(1), dim3(BIND_CHUNK), 0, s, dst + i0, c, n);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 void destroy_graphs(sht_batch_s* b) {
   if (b->g_inv) (void)hipGraphExecDestroy(b->g_inv);
   if (b->g_dir) (void)hipGraphExecDestroy(b->g_dir);
@@ -770,7 +796,10 @@ int batch_upload(sht_batch_s* b, hipStream_t s) {
   std::vector<DevPlan> dps(b->n);
   for (int i = 0; i < b->n; ++i) dps[i] = b->plans[i]->dp;
   HIP_TRY(hipMemcpy(b->d_plans, dps.data(), sizeof(DevPlan) * b->n, hipMemcpyHostToDevice));
-  if (b->bound) HIP_TRY(hipMemcpy(b->d_io, b->io_host.data(), sizeof(IoBind) * b->n, hipMemcpyHostToDevice));
+  if (b->bound) {
+    HIP_TRY(write_binds(b->d_io, b->io_host, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
   for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
     if (!b->inv[v].empty())
       HIP_TRY(hipMemcpy(b->d_inv[v], b->inv[v].data(), sizeof(WorkItem) * b->inv[v].size(), hipMemcpyHostToDevice));
@@ -1097,14 +1126,14 @@ int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags
 
 size_t sht_batch_workspace_size(sht_batch_t b) { return b ? b->ws_bytes : 0; }
 
-int sht_batch_bind(sht_batch_t b, void* const* spec, void* const* grid, void* workspace) {
+int sht_batch_bind(sht_batch_t b, void* const* spec, void* const* grid, void* workspace, void* stream) {
   if (!b || !spec || !grid || !workspace) return SHT_EINVAL;
   std::vector<IoBind> io(b->n);
   for (int i = 0; i < b->n; ++i) {
     if (!spec[i] || !grid[i]) return SHT_EINVAL;
     io[i] = IoBind{spec[i], grid[i], (char*)workspace + b->ws_off[i], nullptr};
   }
-  HIP_TRY(hipMemcpy(b->d_io, io.data(), sizeof(IoBind) * b->n, hipMemcpyHostToDevice));
+  HIP_TRY(write_binds(b->d_io, io, (hipStream_t)stream));
   b->io_host = io;
   b->bound = true;
   return SHT_OK;

@@ -846,7 +846,7 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
     __syncthreads();
     if (jc + 1 < nj) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) fr[e] = fr_next[e];
+      for (int e = 0; e < 4; ++e) fr[e] = fr_next[e];
       fetch(jc + 1);
       if (jc + 2 < nj) fetch_rows(jc + 2, fr_next);
     }

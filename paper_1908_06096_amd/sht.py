@@ -67,7 +67,7 @@ _SIGNATURES = {
                                         ctypes.c_int, ctypes.c_void_p]),
     "sht_batch_workspace_size": (ctypes.c_size_t, [ctypes.c_void_p]),
     "sht_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
-                                      ctypes.c_void_p]),
+                                      ctypes.c_void_p, ctypes.c_void_p]),
     "sht_batch_inverse": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sht_batch_direct": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sht_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
@@ -259,18 +259,42 @@ class Plan:
         return self._ptr(t, self.workspace_bytes, "workspace", dtype=torch.uint8)
 
     # ---- transforms ----
+    def _temporaries(self, stream, device, **make):
+        """Buffers the caller did not pass, allocated on the stream the
+        library will use (so the caching allocator does not hand them to
+        other streams' work while the kernels still run)."""
+        import torch
+
+        st = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            return {k: f(device) for k, f in make.items()}
+
     def inverse(self, spec, grid=None, workspace=None, stream=None):
-        """Synthesis spectral -> grid, enqueued on the current stream."""
-        grid = self.empty_grid(spec.device) if grid is None else grid
-        workspace = self.empty_workspace(spec.device) if workspace is None else workspace
+        """Synthesis spectral -> grid, enqueued on ``stream`` (default: the
+        current stream)."""
+        tmp = {}
+        if grid is None:
+            tmp["grid"] = self.empty_grid
+        if workspace is None:
+            tmp["ws"] = self.empty_workspace
+        t = self._temporaries(stream, spec.device, **tmp) if tmp else {}
+        grid = t.get("grid", grid)
+        workspace = t.get("ws", workspace)
         _check(self._lib.sht_inverse(self._h, self._spec(spec), self._grid(grid), self._ws(workspace),
                                      _stream_handle(stream)), "sht_inverse")
         return grid
 
     def direct(self, grid, spec=None, workspace=None, stream=None):
-        """Analysis grid -> spectral, enqueued on the current stream."""
-        spec = self.empty_spec(grid.device) if spec is None else spec
-        workspace = self.empty_workspace(grid.device) if workspace is None else workspace
+        """Analysis grid -> spectral, enqueued on ``stream`` (default: the
+        current stream)."""
+        tmp = {}
+        if spec is None:
+            tmp["spec"] = self.empty_spec
+        if workspace is None:
+            tmp["ws"] = self.empty_workspace
+        t = self._temporaries(stream, grid.device, **tmp) if tmp else {}
+        spec = t.get("spec", spec)
+        workspace = t.get("ws", workspace)
         _check(self._lib.sht_direct(self._h, self._grid(grid), self._spec(spec), self._ws(workspace),
                                     _stream_handle(stream)), "sht_direct")
         return spec
@@ -334,17 +358,21 @@ class Batch:
     def workspace_bytes(self):
         return int(self._lib.sht_batch_workspace_size(self._h))
 
-    def bind(self, specs, grids, workspace=None):
+    def bind(self, specs, grids, workspace=None, stream=None):
+        """Bind every transform's buffers, in stream order on ``stream``
+        (default: the current stream)."""
         import torch
 
         if workspace is None:
-            workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
+            with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+                workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device="cuda")
         n = len(self.plans)
         sp = (ctypes.c_void_p * n)(*[p._spec(s).value for p, s in zip(self.plans, specs)])
         gp = (ctypes.c_void_p * n)(*[p._grid(g).value for p, g in zip(self.plans, grids)])
         if workspace.numel() < self.workspace_bytes or workspace.dtype != torch.uint8:
             raise ValueError("workspace too small")
-        _check(self._lib.sht_batch_bind(self._h, sp, gp, ctypes.c_void_p(workspace.data_ptr())), "sht_batch_bind")
+        _check(self._lib.sht_batch_bind(self._h, sp, gp, ctypes.c_void_p(workspace.data_ptr()),
+                                        _stream_handle(stream)), "sht_batch_bind")
         self._bound = (list(specs), list(grids), workspace)
         return workspace
 

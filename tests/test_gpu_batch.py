@@ -89,6 +89,36 @@ def test_graph_replays_and_rebinding(sht):
         p.close()
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_rebinding_is_stream_ordered(sht, graph):
+    # bind, inverse, bind, direct, bind, inverse enqueued on one non-blocking
+    # stream with no host synchronisation in between: each run uses the
+    # buffers bound just before it
+    plans, specs, _ = _make(sht, "fp32")
+    ref_g, ref_b = _alone(plans, specs)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        grids = [p.empty_grid() for p in plans]
+        grids2 = [p.empty_grid().fill_(float("nan")) for p in plans]
+        backs = [p.empty_spec().fill_(float("nan")) for p in plans]
+        b = sht.Batch(plans, persistent=True, graph=graph)
+        b.bind(specs, grids)
+        b.inverse()
+        b.bind(backs, grids)
+        b.direct()
+        b.bind(specs, grids2)
+        b.inverse()
+        stream.synchronize()
+        for g, g2, r in zip(grids, grids2, ref_g):
+            assert torch.equal(g, r)
+            assert torch.equal(g2, r)
+        for s_, r in zip(backs, ref_b):
+            assert torch.equal(s_, r)
+        b.close()
+    for p in plans:
+        p.close()
+
+
 def test_tuned_batch_equals_alone(sht):
     plans, specs, _ = _make(sht, "fp32")
     ref_g, ref_b = _alone(plans, specs)
