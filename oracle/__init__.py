@@ -2,6 +2,7 @@
 only: used by the tests, the smoke check and the benchmark's CPU baseline,
 never by the product path)."""
 
+from . import vector_oracle  # noqa: F401
 from .sht_oracle import (  # noqa: F401
     dft_analysis,
     dft_synthesis,
