@@ -94,8 +94,16 @@ enum sht_status {
   SHT_EINVAL = -1,       /* bad argument (null pointer, out-of-range value) */
   SHT_EUNSUPPORTED = -2, /* (truncation, grid, precision) not supported     */
   SHT_ENOMEM = -3,       /* device allocation failed at plan creation       */
-  SHT_EHIP = -4          /* a HIP call failed; see sht_last_hip_error()     */
+  SHT_EHIP = -4,         /* a HIP call failed; see sht_last_hip_error()     */
+  SHT_ESCRATCH = -5      /* sht_transform_static: the plan's workspace is
+                            larger than SHT_STATIC_SCRATCH_BYTES            */
 };
+
+/* Transform directions (sht_transform_static). */
+enum sht_direction { SHT_DIR_INVERSE = 0, SHT_DIR_DIRECT = 1 };
+
+/* Size of the per-device scratch array behind sht_transform_static. */
+#define SHT_STATIC_SCRATCH_BYTES (64u << 20)
 
 typedef struct sht_plan_s* sht_plan_t;
 
@@ -185,6 +193,23 @@ int sht_inverse(sht_plan_t plan, const void* spec, void* grid, void* workspace,
  * sht_fourier_analysis then sht_legendre_direct.  Asynchronous. */
 int sht_direct(sht_plan_t plan, const void* grid, void* spec, void* workspace,
                void* hip_stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transform as sht_inverse (direction SHT_DIR_INVERSE, `in` = spec, `out` =
+ * grid) or sht_direct (SHT_DIR_DIRECT, `in` = grid, `out` = spec), with the
+ * workspace taken from a fixed array of SHT_STATIC_SCRATCH_BYTES that the
+ * library holds in each GPU's memory (reserved when the library is loaded,
+ * kept until the process ends) instead of from the caller.  Results are
+ * bitwise those of sht_inverse / sht_direct.  Calls no allocating routine;
+ * the first call on a device looks the array's device address up once.
+ * SHT_ESCRATCH if sht_workspace_size(plan) exceeds the array (64 MiB holds,
+ * for example, T399 full grid with up to 16 fields in FP64, or TCo399 with
+ * up to 16 fields in FP32).  Every call on one GPU shares that GPU's array:
+ * calls whose executions overlap on one GPU (other streams, other threads)
+ * race and give undefined results; order them.  Asynchronous, like
+ * sht_inverse. */
+int sht_transform_static(sht_plan_t plan, int direction, const void* in, void* out, void* hip_stream);
 
 /* Stage 1 of synthesis: per m, S_m = Pbar_even a_even and A_m = Pbar_odd
  * a_odd over the north rings carrying m, then c(ring j) = S + A and

@@ -173,6 +173,11 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 }  // namespace
 
+int shtmi::hip_status(hipError_t e) {
+  (void)hipGetLastError();
+  return hip_fail(e);
+}
+
 // Device tables of a (truncation, grid, precision): geometry metadata,
 // latitudes and weights, Pbar tables, FFT tables.  Shared by every plan made
 // from the same base plan; freed with the last of them.
@@ -1251,6 +1256,7 @@ const char* sht_strerror(int status) {
     case SHT_EUNSUPPORTED: return "unsupported truncation, grid or precision";
     case SHT_ENOMEM: return "device allocation failed";
     case SHT_EHIP: return "HIP runtime error";
+    case SHT_ESCRATCH: return "workspace larger than the library's static scratch";
     default: return "unknown status";
   }
 }

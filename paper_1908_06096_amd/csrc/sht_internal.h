@@ -207,6 +207,10 @@ struct DevPlan {
   int64_t tab_plane;    // element offset of the lo plane of a BF16 split table
 };
 
+// Records a failed HIP call as the calling thread's last HIP error (see
+// sht_last_hip_error) and returns SHT_EHIP (capi.hip).
+int hip_status(hipError_t e);
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the .hip files)
 // ---------------------------------------------------------------------------

@@ -17,6 +17,8 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libshtmi.so
 GRIDS = {"full": 0, "octahedral": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 TILES = {"c128": 0, "c64": 1, "c32": 2}
+DIRECTIONS = {"inverse": 0, "direct": 1}
+STATIC_SCRATCH_BYTES = 64 << 20
 BATCH_PERSISTENT = 1
 BATCH_GRAPH = 2
 
@@ -73,6 +75,8 @@ _SIGNATURES = {
     "sht_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sht_batch_tiles": (ctypes.c_int, [ctypes.c_void_p, _c_int_p]),
     "sht_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sht_transform_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "sht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "sht_last_hip_error": (ctypes.c_int, []),
 }
@@ -298,6 +302,18 @@ class Plan:
         _check(self._lib.sht_direct(self._h, self._grid(grid), self._spec(spec), self._ws(workspace),
                                     _stream_handle(stream)), "sht_direct")
         return spec
+
+    def transform_static(self, direction, x, out, stream=None):
+        """``inverse`` (x = spec, out = grid) or ``direct`` (x = grid, out =
+        spec) with the library's per-device static scratch as the workspace:
+        allocates nothing.  Calls that overlap on one GPU race."""
+        if direction == "inverse":
+            a, b = self._spec(x), self._grid(out)
+        else:
+            a, b = self._grid(x), self._spec(out)
+        _check(self._lib.sht_transform_static(self._h, DIRECTIONS[direction], a, b, _stream_handle(stream)),
+               "sht_transform_static")
+        return out
 
     def legendre_inverse(self, spec, workspace, stream=None):
         _check(self._lib.sht_legendre_inverse(self._h, self._spec(spec), self._ws(workspace),

@@ -38,7 +38,7 @@ def test_binding_covers_exactly_the_header():
 
 def test_strerror_texts():
     lib = sht.library()
-    for code in (0, -1, -2, -3, -4):
+    for code in (0, -1, -2, -3, -4, -5):
         assert lib.sht_strerror(code)
     assert b"unknown" in lib.sht_strerror(-99)
 
@@ -64,3 +64,4 @@ def test_null_handles_rejected():
     assert lib.sht_inverse(None, None, None, None, None) == -1
     assert lib.sht_direct(None, None, None, None, None) == -1
     assert lib.sht_workspace_size(None) == 0
+    assert lib.sht_transform_static(None, 0, None, None, None) == -1
