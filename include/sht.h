@@ -123,7 +123,16 @@ typedef struct sht_info {
   int32_t elem_bytes;    /* 8 for SHT_FP64, 4 otherwise */
   int32_t tile;          /* Legendre column-tile variant in use (enum sht_tile) */
   int64_t own_bytes;     /* device bytes of the plan without the shared tables */
+  int32_t vector;        /* 1 for plans of sht_plan_create_vector, else 0 */
+  int32_t degree;        /* highest degree of the Pbar tables: N, or N + 1 for vector plans */
 } sht_info;
+
+/* Pointwise spectral operators (sht_spectral_op), on the unit sphere. */
+enum sht_op {
+  SHT_OP_DLAMBDA = 0,      /* d/dlambda:  a_n^m -> i m a_n^m                 */
+  SHT_OP_LAPLACIAN = 1,    /* Laplacian:  a_n^m -> -n (n + 1) a_n^m           */
+  SHT_OP_INV_LAPLACIAN = 2 /* its inverse: a_n^m -> -a_n^m / (n (n + 1)), 0 at n = 0 */
+};
 
 /* Column-tile variants of the Legendre products: the 2F real columns of a
  * product are cut into tiles of 128, 64 or 32 columns.  Plans start with the
@@ -210,6 +219,67 @@ int sht_direct(sht_plan_t plan, const void* grid, void* spec, void* workspace,
  * race and give undefined results; order them.  Asynchronous, like
  * sht_inverse. */
 int sht_transform_static(sht_plan_t plan, int direction, const void* in, void* out, void* hip_stream);
+
+/* ---- Derivatives and vector (wind) transforms ----
+ *
+ * The report works in spectral space because derivatives become pointwise
+ * multiplications there (section 4.4.1).  On the unit sphere (multiply
+ * winds by 1/a, vorticity and divergence by 1/a for radius a), with
+ * mu = sin(latitude), U = u cos(lat), V = v cos(lat), stream function psi
+ * and velocity potential chi (vorticity zeta = Lap psi, divergence
+ * D = Lap chi):
+ *   U = dchi/dlambda - (1 - mu^2) dpsi/dmu,
+ *   V = dpsi/dlambda + (1 - mu^2) dchi/dmu.
+ * The mu derivative is taken in spectral space with the derivative identity
+ *   (1 - mu^2) dPbar_n^m/dmu = (n+1) e_n Pbar_{n-1}^m - n e_{n+1} Pbar_{n+1}^m,
+ *   e_n = sqrt((n^2 - m^2) / (4 n^2 - 1)),
+ * so U and V are syntheses of degree up to N + 1 with the Pbar tables
+ * alone (extended by one degree).  The analysis is the Gaussian quadrature
+ * below with a second table, H_n^m = (1 - mu^2) dPbar_n^m/dmu of degree
+ * <= N, computed in float64 from the same identity at plan time (forming
+ * the H sums from Pbar projections of neighbouring degrees instead would
+ * cancel, and multiply the rounding of the products by up to ~N).
+ * zeta_0^0 and D_0^0 do not enter the winds and are returned as 0; Im of
+ * every m = 0 coefficient is ignored on input and 0 on output.
+ *
+ * Layouts: vortdiv [2][F][nspec] complex (the F vorticity fields, then the
+ * F divergence fields), uv [2][F][npts] real (the F U fields, then the F V
+ * fields), nspec and npts of truncation N. */
+
+/* A plan for F vector fields (2F grid components): Pbar tables to degree
+ * N + 1 and H tables to degree N (each the size of a scalar plan's table),
+ * the analysis weight w_j / (1 - mu_j^2) per ring, work lists for 2F
+ * components.  Arguments and errors as sht_plan_create.  Such a plan serves
+ * sht_vector_inverse, sht_vector_direct, sht_gradient and sht_spectral_op;
+ * the scalar calls (sht_inverse, stages, batches) reject it with
+ * SHT_EINVAL.  sht_plan_create_like makes a vector plan from a vector
+ * base.  Its sht_workspace_size covers the Fourier buffer of 2F components
+ * and two arrays of 2F wind coefficients of degree N + 1. */
+int sht_plan_create_vector(sht_plan_t* out, int truncation, int grid, int nfields,
+                           int precision, void* hip_stream);
+
+/* Winds from vorticity and divergence: vortdiv [2][F][nspec] -> uv
+ * [2][F][npts].  Asynchronous on `hip_stream`; no allocation. */
+int sht_vector_inverse(sht_plan_t plan, const void* vortdiv, void* uv, void* workspace,
+                       void* hip_stream);
+
+/* Vorticity and divergence from winds: uv [2][F][npts] -> vortdiv
+ * [2][F][nspec], by Gaussian quadrature:
+ *   zeta_n^m = sum_j w_j/(1-mu_j^2) [i m V_{j,m} Pbar_n^m(mu_j) + U_{j,m} H_n^m(mu_j)],
+ *   D_n^m    = sum_j w_j/(1-mu_j^2) [i m U_{j,m} Pbar_n^m(mu_j) - V_{j,m} H_n^m(mu_j)],
+ * H = (1 - mu^2) dPbar/dmu, U_{j,m}, V_{j,m} the ring DFT coefficients
+ * (1/nlon_j) sum_k (.) e^{-i m lambda_k}.  Asynchronous; no allocation. */
+int sht_vector_direct(sht_plan_t plan, const void* uv, void* vortdiv, void* workspace,
+                      void* hip_stream);
+
+/* cos(lat) times the gradient of F scalar fields: spec [F][nspec] -> uv
+ * [2][F][npts] with U = df/dlambda, V = (1 - mu^2) df/dmu (the wind of
+ * velocity potential f).  Asynchronous; no allocation. */
+int sht_gradient(sht_plan_t plan, const void* spec, void* uv, void* workspace, void* hip_stream);
+
+/* `op` (enum sht_op) on `count` spectral fields [count][nspec] of the plan's
+ * truncation and data type; in == out is allowed.  Asynchronous. */
+int sht_spectral_op(sht_plan_t plan, int op, int count, const void* in, void* out, void* hip_stream);
 
 /* Stage 1 of synthesis: per m, S_m = Pbar_even a_even and A_m = Pbar_odd
  * a_odd over the north rings carrying m, then c(ring j) = S + A and

@@ -193,8 +193,14 @@ struct SharedTables {
 };
 
 struct sht_plan_s {
+  // N: truncation (fixes the grid and the per-ring Fourier truncation).
+  // ndeg: highest degree of the tables and of the internal spectral layout
+  // (N, or N + 1 for vector plans, whose wind coefficients reach N + 1).
+  // F: fields the kernels transform (2 Fv components for vector plans).
   int N = 0, grid = 0, F = 0, prec = 0, nlat = 0, nh = 0, Fp = 0;
+  int vec = 0, ndeg = 0, Fv = 0;
   int64_t npts = 0, nspec = 0, nfour = 0;
+  int64_t nspec_d = 0;  // internal spectral layout (degree ndeg)
   int elem = 8;
   int variant = TILE_C128;
   std::vector<RingInfo> rings;
@@ -221,6 +227,15 @@ struct sht_plan_s {
   FftItem* d_ana = nullptr;
   MInfo* d_ms = nullptr;
   FftClass* d_cls = nullptr;
+  // vector plans: the H = (1 - mu^2) dPbar/dmu table of degree <= N (planes
+  // by the parity of H: odd n - m in plane 0), its per-m layout, and the
+  // descriptor the analysis product takes to run over it
+  std::vector<MInfo> hms;
+  int64_t htab_plane = 0;
+  size_t htab_bytes = 0;
+  MInfo* d_hms = nullptr;
+  DevPlan dph{};
+  DevPlan* d_self_h = nullptr;
 };
 
 namespace {
@@ -433,7 +448,9 @@ int build_host(sht_plan_s* p) {
   }
   p->nh = p->nlat / 2;
   p->Fp = (int)round_up(p->F, FPAD);
+  const int D = p->ndeg;
   p->nspec = (int64_t)(N + 1) * (N + 2) / 2;
+  p->nspec_d = (int64_t)(D + 1) * (D + 2) / 2;
   p->rings.resize(p->nlat);
   p->ring_off.assign(p->nlat + 1, 0);
   p->four_row.assign(p->nlat + 1, 0);
@@ -515,20 +532,39 @@ int build_host(sht_plan_s* p) {
     mi.first_ring = first;
     mi.L = p->nh - first;
     mi.Lp = (int)round_up(mi.L, ROWPAD);
-    mi.K[0] = (N - m) / 2 + 1;
-    mi.K[1] = (N - m + 1) / 2;
+    mi.K[0] = (D - m) / 2 + 1;
+    mi.K[1] = (D - m + 1) / 2;
     mi.Kp[0] = (int)round_up(mi.K[0], KCH);
     mi.Kp[1] = (int)round_up(mi.K[1], KCH);
     mi.toff[0] = toff;
     mi.toff[1] = toff + (int64_t)mi.Kp[0] * mi.Lp;
     toff = mi.toff[1] + (int64_t)mi.Kp[1] * mi.Lp;
-    mi.spec_off = (int64_t)m * (2 * N + 3 - m) / 2;
+    mi.spec_off = (int64_t)m * (2 * D + 3 - m) / 2;
     p->max_Lp = std::max(p->max_Lp, mi.Lp);
     p->ms.push_back(mi);
   }
   p->tab_plane = toff;
   const int tab_elem = (p->prec == SHT_FP64) ? 8 : 4;  // BF16 split: two 2-byte planes
   p->tab_bytes = (size_t)toff * tab_elem;
+  if (p->vec) {
+    // H table: degrees m..N; plane 0 odd n - m, plane 1 even n - m.  Its
+    // products write degree n at spec_off + parity + 2k of the wind layout
+    // (degree N + 1), i.e. n - 1 (odd) or n + 1 (even), inside m's block.
+    int64_t hoff = 0;
+    for (const MInfo& mi : p->ms) {
+      MInfo hi = mi;
+      hi.K[0] = (N - mi.m + 1) / 2;
+      hi.K[1] = (N - mi.m) / 2 + 1;
+      hi.Kp[0] = (int)round_up(hi.K[0], KCH);
+      hi.Kp[1] = (int)round_up(hi.K[1], KCH);
+      hi.toff[0] = hoff;
+      hi.toff[1] = hoff + (int64_t)hi.Kp[0] * hi.Lp;
+      hoff = hi.toff[1] + (int64_t)hi.Kp[1] * hi.Lp;
+      p->hms.push_back(hi);
+    }
+    p->htab_plane = hoff;
+    p->htab_bytes = (size_t)hoff * tab_elem;
+  }
 
   // ---- work lists (m ascending = cost descending for both products) ----
   p->variant = default_variant(p->prec, p->F);
@@ -560,8 +596,9 @@ void list_capacity(const sht_plan_s* p, size_t* inv_cap, size_t* dir_cap) {
 int build_own(sht_plan_s* p, hipStream_t s) {
   size_t inv_cap, dir_cap;
   list_capacity(p, &inv_cap, &dir_cap);
-  const size_t parts[5] = {sizeof(DevPlan), sizeof(WorkItem) * inv_cap, sizeof(WorkItem) * dir_cap,
-                           sizeof(FftItem) * p->syn_items.size(), sizeof(FftItem) * p->ana_items.size()};
+  const size_t parts[6] = {sizeof(DevPlan), sizeof(WorkItem) * inv_cap, sizeof(WorkItem) * dir_cap,
+                           sizeof(FftItem) * p->syn_items.size(), sizeof(FftItem) * p->ana_items.size(),
+                           p->vec ? sizeof(DevPlan) : 0};
   size_t total = 0;
   for (size_t q : parts) total += align256(q);
   if (hipMalloc(&p->arena, total) != hipSuccess) {
@@ -571,8 +608,8 @@ int build_own(sht_plan_s* p, hipStream_t s) {
   }
   p->arena_bytes = total;
   char* o = (char*)p->arena;
-  void* ptr[5];
-  for (int i = 0; i < 5; ++i) {
+  void* ptr[6];
+  for (int i = 0; i < 6; ++i) {
     ptr[i] = o;
     o += align256(parts[i]);
   }
@@ -581,7 +618,9 @@ int build_own(sht_plan_s* p, hipStream_t s) {
   p->d_dir = (WorkItem*)ptr[2];
   p->d_syn = (FftItem*)ptr[3];
   p->d_ana = (FftItem*)ptr[4];
+  p->d_self_h = p->vec ? (DevPlan*)ptr[5] : nullptr;
   HIP_TRY(hipMemcpyAsync(p->d_self, &p->dp, sizeof(DevPlan), hipMemcpyHostToDevice, s));
+  if (p->vec) HIP_TRY(hipMemcpyAsync(p->d_self_h, &p->dph, sizeof(DevPlan), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(p->d_inv, p->inv_items.data(), sizeof(WorkItem) * p->inv_items.size(), hipMemcpyHostToDevice,
                          s));
   HIP_TRY(hipMemcpyAsync(p->d_dir, p->dir_items.data(), sizeof(WorkItem) * p->dir_items.size(), hipMemcpyHostToDevice,
@@ -592,7 +631,7 @@ int build_own(sht_plan_s* p, hipStream_t s) {
 }
 
 int build_device(sht_plan_s* p, hipStream_t s) {
-  void *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft;
+  void *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft, *v_wa, *v_hms, *v_htab;
   struct Part {
     void** dst;
     size_t bytes;
@@ -605,6 +644,9 @@ int build_device(sht_plan_s* p, hipStream_t s) {
       {&v_w, sizeof(double) * p->nlat},
       {&v_tab, p->tab_bytes},
       {&v_fft, p->fft_bytes},
+      {&v_wa, p->vec ? sizeof(double) * p->nlat : 0},
+      {&v_hms, sizeof(MInfo) * p->hms.size()},
+      {&v_htab, p->htab_bytes},
   };
   size_t total = 0;
   for (const Part& q : parts) total += align256(q.bytes);
@@ -621,32 +663,43 @@ int build_device(sht_plan_s* p, hipStream_t s) {
     o += align256(q.bytes);
   }
   DevPlan& d = p->dp;
-  d.N = p->N;
+  d.N = p->ndeg;
   d.nlat = p->nlat;
   d.nh = p->nh;
   d.F = p->F;
   d.Fp = p->Fp;
   d.npts = p->npts;
-  d.nspec = p->nspec;
+  d.nspec = p->nspec_d;
   d.rings = (const RingInfo*)v_rings;
   d.classes = (const FftClass*)v_cls;
   d.ms = (const MInfo*)v_ms;
   d.mu = (const double*)v_mu;
   d.w = (const double*)v_w;
+  d.wa = p->vec ? (const double*)v_wa : (const double*)v_w;
   d.tab = v_tab;
   d.fft = v_fft;
   d.tab_plane = p->tab_plane;
   p->d_ms = (MInfo*)v_ms;
   p->d_cls = (FftClass*)v_cls;
+  if (p->vec) {
+    p->d_hms = (MInfo*)v_hms;
+    p->dph = d;
+    p->dph.ms = (const MInfo*)v_hms;
+    p->dph.tab = v_htab;
+    p->dph.tab_plane = p->htab_plane;
+  }
 
   HIP_TRY(hipMemcpyAsync(v_rings, p->rings.data(), parts[0].bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(v_cls, p->classes.data(), parts[1].bytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemcpyAsync(v_ms, p->ms.data(), parts[2].bytes, hipMemcpyHostToDevice, s));
+  if (p->vec) HIP_TRY(hipMemcpyAsync(v_hms, p->hms.data(), sizeof(MInfo) * p->hms.size(), hipMemcpyHostToDevice, s));
   int rc = build_own(p, s);
   if (rc != SHT_OK) return rc;
 
   HIP_TRY(launch_gauss(p->nlat, (double*)v_mu, (double*)v_w, s));
-  HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane, s));
+  if (p->vec) HIP_TRY(launch_analysis_weight(p->nlat, (const double*)v_mu, (const double*)v_w, (double*)v_wa, s));
+  HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane,
+                             p->vec ? p->d_hms : nullptr, v_htab, p->htab_plane, p->N, s));
   HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls, (int)p->classes.size(), p->classes.data(), v_fft, s));
   HIP_TRY(ensure_lds(std::max(p->lds_syn, p->lds_ana)));
   HIP_TRY(hipStreamSynchronize(s));
@@ -881,19 +934,22 @@ int batch_run(sht_batch_s* b, hipStream_t s, bool inverse) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int precision, void* hip_stream) {
+int plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int precision, bool vec, void* hip_stream) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
-  if (truncation < 1 || nfields < 1) return SHT_EINVAL;
+  if (truncation < 1 || nfields < 1 || nfields > (vec ? (1 << 29) : (1 << 30))) return SHT_EINVAL;
   if (grid != SHT_GRID_FULL && grid != SHT_GRID_OCTAHEDRAL) return SHT_EINVAL;
   if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_EINVAL;
   sht_plan_s* p = new (std::nothrow) sht_plan_s();
   if (!p) return SHT_ENOMEM;
   p->N = truncation;
   p->grid = grid;
-  p->F = nfields;
+  p->vec = vec ? 1 : 0;
+  p->ndeg = truncation + (vec ? 1 : 0);
+  p->Fv = nfields;
+  p->F = vec ? 2 * nfields : nfields;
   p->prec = precision;
   p->elem = (precision == SHT_FP64) ? 8 : 4;
   int rc = build_host(p);
@@ -910,6 +966,18 @@ int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int 
   return SHT_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int precision, void* hip_stream) {
+  return plan_create(out, truncation, grid, nfields, precision, false, hip_stream);
+}
+
+int sht_plan_create_vector(sht_plan_t* out, int truncation, int grid, int nfields, int precision, void* hip_stream) {
+  return plan_create(out, truncation, grid, nfields, precision, true, hip_stream);
+}
+
 int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hip_stream) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
@@ -919,6 +987,13 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->N = base->N;
   p->grid = base->grid;
   p->prec = base->prec;
+  p->vec = base->vec;
+  p->ndeg = base->ndeg;
+  p->nspec_d = base->nspec_d;
+  p->hms = base->hms;
+  p->htab_plane = base->htab_plane;
+  p->htab_bytes = base->htab_bytes;
+  p->d_hms = base->d_hms;
   p->elem = base->elem;
   p->nlat = base->nlat;
   p->nh = base->nh;
@@ -943,11 +1018,15 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->tables = base->tables;
   p->d_ms = base->d_ms;
   p->d_cls = base->d_cls;
-  p->F = nfields;
-  p->Fp = (int)round_up(nfields, FPAD);
+  p->Fv = nfields;
+  p->F = p->vec ? 2 * nfields : nfields;
+  p->Fp = (int)round_up(p->F, FPAD);
   p->dp = base->dp;
   p->dp.F = p->F;
   p->dp.Fp = p->Fp;
+  p->dph = base->dph;
+  p->dph.F = p->F;
+  p->dph.Fp = p->Fp;
   p->variant = default_variant(p->prec, p->F);
   legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
   {
@@ -987,7 +1066,7 @@ int sht_plan_info(sht_plan_t p, sht_info* out) {
   std::memset(out, 0, sizeof(*out));
   out->truncation = p->N;
   out->grid = p->grid;
-  out->nfields = p->F;
+  out->nfields = p->Fv;
   out->precision = p->prec;
   out->nlat = p->nlat;
   out->fpad = p->Fp;
@@ -995,11 +1074,13 @@ int sht_plan_info(sht_plan_t p, sht_info* out) {
   out->nspec = p->nspec;
   out->nfour = p->nfour;
   out->workspace_bytes = (int64_t)sht_workspace_size(p);
-  out->table_bytes = (int64_t)p->tab_bytes;
+  out->table_bytes = (int64_t)(p->tab_bytes + p->htab_bytes);
   out->plan_bytes = (int64_t)p->arena_bytes + (p->tables ? (int64_t)p->tables->bytes : 0);
   out->own_bytes = (int64_t)p->arena_bytes;
   out->elem_bytes = p->elem;
   out->tile = p->variant;
+  out->vector = p->vec;
+  out->degree = p->ndeg;
   return SHT_OK;
 }
 
@@ -1022,7 +1103,7 @@ int sht_plan_legendre_table(sht_plan_t p, int m, double* out, int32_t* first_rin
   const MInfo& mi = p->ms[m];
   if (first_ring) *first_ring = mi.first_ring;
   if (!out) return SHT_OK;
-  const size_t n = (size_t)mi.L * (p->N - m + 1);
+  const size_t n = (size_t)mi.L * (p->ndeg - m + 1);
   if (n == 0) return SHT_OK;
   double* tmp = nullptr;
   HIP_TRY(hipMalloc(&tmp, n * sizeof(double)));
@@ -1048,49 +1129,130 @@ int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
 
 size_t sht_workspace_size(sht_plan_t p) {
   if (!p) return 0;
-  return (size_t)p->nfour * p->Fp * 2 * p->elem;
+  const size_t four = (size_t)p->nfour * p->Fp * 2 * p->elem;
+  if (!p->vec) return four;
+  // vector plans: the Fourier buffer, then two arrays of wind coefficients
+  // of degree N + 1 (synthesis input / Pbar projections, and H projections)
+  return align256(four) + 2 * align256((size_t)p->F * p->nspec_d * 2 * p->elem);
 }
 
-int sht_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* stream) {
-  if (!p || !spec || !four) return SHT_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// The stages on a plan's internal layouts (degree ndeg, F fields or
+// components); the public stage calls add the checks of the scalar layout.
+int stage_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* stream) {
   HIP_TRY(launch_legendre_inverse(p->d_self, p->prec, p->variant, p->d_inv, (int)p->inv_items.size(), nullptr,
                                   bind_of(spec, nullptr, four), (int)p->inv_items.size(), (hipStream_t)stream));
   return SHT_OK;
 }
 
-int sht_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream) {
-  if (!p || !four || !grid) return SHT_EINVAL;
+int stage_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream) {
   HIP_TRY(fft_launch_tiers(true, p->d_self, p->prec, p->d_syn, p->syn_off, nullptr,
                            bind_of(nullptr, grid, four), p->lds_syn_t, (hipStream_t)stream));
   return SHT_OK;
 }
 
-int sht_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* stream) {
-  if (!p || !four || !grid) return SHT_EINVAL;
+int stage_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* stream) {
   HIP_TRY(fft_launch_tiers(false, p->d_self, p->prec, p->d_ana, p->ana_off, nullptr,
                            bind_of(nullptr, grid, four), p->lds_ana_t, (hipStream_t)stream));
   return SHT_OK;
 }
 
-int sht_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream) {
-  if (!p || !spec || !four) return SHT_EINVAL;
+int stage_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream) {
   HIP_TRY(launch_legendre_direct(p->d_self, p->prec, p->variant, p->d_dir, (int)p->dir_items.size(), nullptr,
                                  bind_of(spec, nullptr, four), (int)p->dir_items.size(), (hipStream_t)stream));
   return SHT_OK;
 }
 
+bool scalar_plan(sht_plan_t p) { return p && !p->vec; }
+bool vector_plan(sht_plan_t p) { return p && p->vec; }
+
+// The wind-coefficient arrays of a vector plan's workspace (after the
+// Fourier buffer): 0 = synthesis input / Pbar projections, 1 = H projections.
+void* wind_spec(sht_plan_t p, void* ws, int which = 0) {
+  return (char*)ws + align256((size_t)p->nfour * p->Fp * 2 * p->elem) +
+         which * align256((size_t)p->F * p->nspec_d * 2 * p->elem);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sht_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* stream) {
+  if (!scalar_plan(p) || !spec || !four) return SHT_EINVAL;
+  return stage_legendre_inverse(p, spec, four, stream);
+}
+
+int sht_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream) {
+  if (!scalar_plan(p) || !four || !grid) return SHT_EINVAL;
+  return stage_fourier_synthesis(p, four, grid, stream);
+}
+
+int sht_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* stream) {
+  if (!scalar_plan(p) || !four || !grid) return SHT_EINVAL;
+  return stage_fourier_analysis(p, grid, four, stream);
+}
+
+int sht_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream) {
+  if (!scalar_plan(p) || !spec || !four) return SHT_EINVAL;
+  return stage_legendre_direct(p, four, spec, stream);
+}
+
 int sht_inverse(sht_plan_t p, const void* spec, void* grid, void* ws, void* stream) {
-  if (!p || !spec || !grid || !ws) return SHT_EINVAL;
-  int rc = sht_legendre_inverse(p, spec, ws, stream);
+  if (!scalar_plan(p) || !spec || !grid || !ws) return SHT_EINVAL;
+  int rc = stage_legendre_inverse(p, spec, ws, stream);
   if (rc != SHT_OK) return rc;
-  return sht_fourier_synthesis(p, ws, grid, stream);
+  return stage_fourier_synthesis(p, ws, grid, stream);
 }
 
 int sht_direct(sht_plan_t p, const void* grid, void* spec, void* ws, void* stream) {
-  if (!p || !spec || !grid || !ws) return SHT_EINVAL;
-  int rc = sht_fourier_analysis(p, grid, ws, stream);
+  if (!scalar_plan(p) || !spec || !grid || !ws) return SHT_EINVAL;
+  int rc = stage_fourier_analysis(p, grid, ws, stream);
   if (rc != SHT_OK) return rc;
-  return sht_legendre_direct(p, ws, spec, stream);
+  return stage_legendre_direct(p, ws, spec, stream);
+}
+
+int sht_vector_inverse(sht_plan_t p, const void* vortdiv, void* uv, void* ws, void* stream) {
+  if (!vector_plan(p) || !vortdiv || !uv || !ws) return SHT_EINVAL;
+  void* wind = wind_spec(p, ws);
+  HIP_TRY(launch_uv_from_potentials(p->N, p->Fv, false, p->prec, vortdiv, wind, (hipStream_t)stream));
+  int rc = stage_legendre_inverse(p, wind, ws, stream);
+  if (rc != SHT_OK) return rc;
+  return stage_fourier_synthesis(p, ws, uv, stream);
+}
+
+int sht_gradient(sht_plan_t p, const void* spec, void* uv, void* ws, void* stream) {
+  if (!vector_plan(p) || !spec || !uv || !ws) return SHT_EINVAL;
+  void* wind = wind_spec(p, ws);
+  HIP_TRY(launch_uv_from_potentials(p->N, p->Fv, true, p->prec, spec, wind, (hipStream_t)stream));
+  int rc = stage_legendre_inverse(p, wind, ws, stream);
+  if (rc != SHT_OK) return rc;
+  return stage_fourier_synthesis(p, ws, uv, stream);
+}
+
+int sht_vector_direct(sht_plan_t p, const void* uv, void* vortdiv, void* ws, void* stream) {
+  if (!vector_plan(p) || !vortdiv || !uv || !ws) return SHT_EINVAL;
+  void* pw = wind_spec(p, ws, 0);
+  void* hw = wind_spec(p, ws, 1);
+  int rc = stage_fourier_analysis(p, uv, ws, stream);
+  if (rc != SHT_OK) return rc;
+  rc = stage_legendre_direct(p, ws, pw, stream);
+  if (rc != SHT_OK) return rc;
+  // the same product over the H table
+  HIP_TRY(launch_legendre_direct(p->d_self_h, p->prec, p->variant, p->d_dir, (int)p->dir_items.size(), nullptr,
+                                 bind_of(hw, nullptr, ws), (int)p->dir_items.size(), (hipStream_t)stream));
+  HIP_TRY(launch_vortdiv_from_projections(p->N, p->Fv, p->prec, pw, hw, vortdiv, (hipStream_t)stream));
+  return SHT_OK;
+}
+
+int sht_spectral_op(sht_plan_t p, int op, int count, const void* in, void* out, void* stream) {
+  if (!p || !in || !out || count < 0) return SHT_EINVAL;
+  if (op != SHT_OP_DLAMBDA && op != SHT_OP_LAPLACIAN && op != SHT_OP_INV_LAPLACIAN) return SHT_EINVAL;
+  if (count == 0) return SHT_OK;
+  HIP_TRY(launch_spectral_op(p->N, count, op, p->prec, in, out, (hipStream_t)stream));
+  return SHT_OK;
 }
 
 int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags, void* stream) {
@@ -1098,7 +1260,7 @@ int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags
   *out = nullptr;
   if (!plans || n < 1 || (flags & ~(SHT_BATCH_PERSISTENT | SHT_BATCH_GRAPH))) return SHT_EINVAL;
   for (int i = 0; i < n; ++i)
-    if (!plans[i] || plans[i]->prec != plans[0]->prec) return SHT_EINVAL;
+    if (!scalar_plan(plans[i]) || plans[i]->prec != plans[0]->prec) return SHT_EINVAL;
   sht_batch_s* b = new (std::nothrow) sht_batch_s();
   if (!b) return SHT_ENOMEM;
   b->n = n;

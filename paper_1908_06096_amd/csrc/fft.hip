@@ -728,7 +728,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   const C* chirp = tabs + cl.chirp_off;
   C* fc = (C*)four;
   const bool blue = cl.bluestein;
-  const T scale = (T)(gload(p.w + ring) / (double)rn.nlon);
+  const T scale = (T)(gload(p.wa + ring) / (double)rn.nlon);
   const int nt = NT >> gs;
   const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
   const int Q = blue ? L : h;

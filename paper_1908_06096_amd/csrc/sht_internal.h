@@ -202,6 +202,7 @@ struct DevPlan {
   const MInfo* ms;
   const double* mu;
   const double* w;
+  const double* wa;     // analysis weight per ring: w (scalar plans), w / (1 - mu^2) (vector plans)
   const void* tab;      // Pbar tables (double, float, or bf16 hi/lo pairs)
   const void* fft;      // complex FFT tables in the data type
   int64_t tab_plane;    // element offset of the lo plane of a BF16 split table
@@ -217,8 +218,11 @@ int hip_status(hipError_t e);
 
 // tables.hip
 hipError_t launch_gauss(int nlat, double* mu, double* w, hipStream_t s);
+// Pbar tables (and, when d_hms is not null, the H = (1 - mu^2) dPbar/dmu
+// tables of degree <= Nh in the layout d_hms describes).
 hipError_t launch_pbar_planes(const DevPlan& p, int prec, const MInfo* d_ms, int nm, int max_Lp,
-                              void* tab, int64_t plane_elems, hipStream_t s);
+                              void* tab, int64_t plane_elems, const MInfo* d_hms, void* htab, int64_t hplane_elems,
+                              int Nh, hipStream_t s);
 hipError_t launch_fft_tables(const DevPlan& p, int prec, const FftClass* d_cls, int ncls,
                              const FftClass* h_cls, void* fft, hipStream_t s);
 hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& mi, int64_t plane,
@@ -236,6 +240,14 @@ void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* di
 bool legendre_variant_supported(int prec, int variant);
 // work groups per CU the kernel of a variant can keep resident
 int legendre_blocks_per_cu(int prec, int variant, bool inverse);
+
+// vector.hip: spectral-space kernels of the derivative and vector
+// transforms (degree N inputs and outputs, degree N + 1 wind coefficients).
+hipError_t launch_uv_from_potentials(int N, int F, bool gradient, int prec, const void* in, void* uv, hipStream_t s);
+hipError_t launch_vortdiv_from_projections(int N, int F, int prec, const void* pw, const void* hw, void* out,
+                                           hipStream_t s);
+hipError_t launch_spectral_op(int N, int count, int op, int prec, const void* in, void* out, hipStream_t s);
+hipError_t launch_analysis_weight(int nlat, const double* mu, const double* w, double* wa, hipStream_t s);
 
 // fft.hip.  Same launch model, one launch per tier: the items of one launch
 // all belong to classes of that tier.

@@ -100,19 +100,46 @@ __device__ inline int64_t tab_index(const MInfo& mi, int par, int r, int k) {
   return mi.toff[par] + (int64_t)(k / KCH) * mi.Lp * KCH + (int64_t)r * KCH + (k % KCH);
 }
 
-__global__ void pbar_kernel(DevPlan p, const MInfo* ms, TabStore st) {
+// Vector plans also store H_k^m = (1 - mu^2) dPbar_k^m/dmu for k = m..Nh
+// (Nh = N, one below the Pbar degree), from the derivative identity
+//   H_k = (k + 1) e_k Pbar_{k-1} - k e_{k+1} Pbar_{k+1},
+//   e_k = sqrt((k^2 - m^2) / (4 k^2 - 1))   (e_m = 0),
+// evaluated as soon as the recurrence has produced Pbar_{k+1}.  H has the
+// opposite parity in mu to Pbar (H_k(-mu) = -(-1)^{k-m} H_k(mu)), so its
+// table puts odd k - m in plane 0 (paired, like Pbar's plane 0, with the
+// symmetric part of the data) and even k - m in plane 1; `hms` describes
+// that layout (K[0] = number of odd k - m, K[1] = number of even).
+__device__ inline double eps_nm(int k, int m) {
+  if (k <= m) return 0.0;
+  return sqrt(((double)k * k - (double)m * m) / (4.0 * (double)k * k - 1.0));
+}
+
+__global__ void pbar_kernel(DevPlan p, const MInfo* ms, TabStore st, const MInfo* hms, TabStore hst, int Nh) {
   const MInfo mi = ms[blockIdx.y];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= mi.Lp) return;
   const int m = mi.m;
   const int N = p.N;
+  const bool with_h = (hms != nullptr);
+  MInfo hi{};
+  if (with_h) hi = hms[blockIdx.y];
   if (r >= mi.L) {
     for (int par = 0; par < 2; ++par)
       for (int k = 0; k < mi.Kp[par]; ++k) st.put(tab_index(mi, par, r, k), 0.0);
+    if (with_h)
+      for (int par = 0; par < 2; ++par)
+        for (int k = 0; k < hi.Kp[par]; ++k) hst.put(tab_index(hi, par, r, k), 0.0);
     return;
   }
   const double x = p.mu[mi.first_ring + r];
   const double s = sqrt((1.0 - x) * (1.0 + x));
+  // H_k once Pbar_{k-1} (pkm1) and Pbar_{k+1} (pkp1) are known
+  auto put_h = [&](int k, double pkm1, double pkp1) {
+    if (!with_h || k > Nh) return;
+    const double h = (k + 1.0) * eps_nm(k, m) * pkm1 - (double)k * eps_nm(k + 1, m) * pkp1;
+    const int d = k - m;
+    hst.put(tab_index(hi, (d & 1) ? 0 : 1, r, d >> 1), h);
+  };
   double pmm = 1.0 / sqrt(2.0);
   for (int k = 1; k <= m; ++k) pmm = sqrt((2.0 * k + 1.0) / (2.0 * k)) * s * pmm;
   st.put(tab_index(mi, 0, r, 0), pmm);
@@ -120,24 +147,31 @@ __global__ void pbar_kernel(DevPlan p, const MInfo* ms, TabStore st) {
     double p2 = pmm;
     double p1 = sqrt(2.0 * m + 3.0) * x * pmm;
     st.put(tab_index(mi, 1, r, 0), p1);
+    put_h(m, 0.0, p1);
     for (int n = m + 2; n <= N; ++n) {
       const double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
       const double b = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
       const double pn = a * (x * p1 - b * p2);
       st.put(tab_index(mi, (n - m) & 1, r, (n - m) >> 1), pn);
+      put_h(n - 1, p2, pn);
       p2 = p1;
       p1 = pn;
     }
   }
   for (int par = 0; par < 2; ++par)
     for (int k = mi.K[par]; k < mi.Kp[par]; ++k) st.put(tab_index(mi, par, r, k), 0.0);
+  if (with_h)
+    for (int par = 0; par < 2; ++par)
+      for (int k = hi.K[par]; k < hi.Kp[par]; ++k) hst.put(tab_index(hi, par, r, k), 0.0);
 }
 
 hipError_t launch_pbar_planes(const DevPlan& p, int prec, const MInfo* d_ms, int nm, int max_Lp,
-                              void* tab, int64_t plane_elems, hipStream_t s) {
+                              void* tab, int64_t plane_elems, const MInfo* d_hms, void* htab, int64_t hplane_elems,
+                              int Nh, hipStream_t s) {
   TabStore st{prec, tab, plane_elems};
+  TabStore hst{prec, htab, hplane_elems};
   const int bs = 64;
-  hipLaunchKernelGGL(pbar_kernel, dim3((max_Lp + bs - 1) / bs, nm), dim3(bs), 0, s, p, d_ms, st);
+  hipLaunchKernelGGL(pbar_kernel, dim3((max_Lp + bs - 1) / bs, nm), dim3(bs), 0, s, p, d_ms, st, d_hms, hst, Nh);
   return hipGetLastError();
 }
 

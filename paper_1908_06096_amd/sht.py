@@ -18,6 +18,7 @@ GRIDS = {"full": 0, "octahedral": 1}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 TILES = {"c128": 0, "c64": 1, "c32": 2}
 DIRECTIONS = {"inverse": 0, "direct": 1}
+OPS = {"dlambda": 0, "laplacian": 1, "inv_laplacian": 2}
 STATIC_SCRATCH_BYTES = 64 << 20
 BATCH_PERSISTENT = 1
 BATCH_GRAPH = 2
@@ -44,6 +45,8 @@ class SHTInfo(ctypes.Structure):
         ("elem_bytes", ctypes.c_int32),
         ("tile", ctypes.c_int32),
         ("own_bytes", ctypes.c_int64),
+        ("vector", ctypes.c_int32),
+        ("degree", ctypes.c_int32),
     ]
 
 
@@ -75,6 +78,13 @@ _SIGNATURES = {
     "sht_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sht_batch_tiles": (ctypes.c_int, [ctypes.c_void_p, _c_int_p]),
     "sht_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sht_plan_create_vector": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "sht_vector_inverse": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "sht_vector_direct": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "sht_gradient": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
+    "sht_spectral_op": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
     "sht_transform_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p]),
     "sht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -129,20 +139,24 @@ def _stream_handle(stream):
 class Plan:
     """A transform plan: truncation N, grid ('full' | 'octahedral'), F fields,
     precision ('fp64' | 'fp32' | 'bf16x3').  Tables are computed on the GPU at
-    creation and stay resident until ``close()``."""
+    creation and stay resident until ``close()``.  With ``vector=True`` the
+    plan serves F vector fields (vorticity / divergence <-> winds, gradients)
+    instead of scalar transforms."""
 
-    def __init__(self, truncation, grid="full", nfields=1, precision="fp64", stream=None, like=None):
+    def __init__(self, truncation, grid="full", nfields=1, precision="fp64", stream=None, like=None, vector=False):
         lib = library()
         self._lib = lib
         self._h = ctypes.c_void_p()
         if like is not None:
             # same tables as `like`, another field count
-            truncation, grid, precision = like.truncation, like.grid, like.precision
+            truncation, grid, precision, vector = like.truncation, like.grid, like.precision, like.vector
             _check(lib.sht_plan_create_like(ctypes.byref(self._h), like._h, int(nfields), _stream_handle(stream)),
                    "sht_plan_create_like")
         else:
-            _check(lib.sht_plan_create(ctypes.byref(self._h), int(truncation), GRIDS[grid], int(nfields),
-                                       PRECISIONS[precision], _stream_handle(stream)), "sht_plan_create")
+            create = lib.sht_plan_create_vector if vector else lib.sht_plan_create
+            _check(create(ctypes.byref(self._h), int(truncation), GRIDS[grid], int(nfields), PRECISIONS[precision],
+                          _stream_handle(stream)), "sht_plan_create_vector" if vector else "sht_plan_create")
+        self.vector = bool(vector)
         info = SHTInfo()
         _check(lib.sht_plan_info(self._h, ctypes.byref(info)), "sht_plan_info")
         self.info = info
@@ -257,6 +271,24 @@ class Plan:
     def _grid(self, t):
         return self._ptr(t, self.nfields * self.npts, "grid")
 
+    def empty_vortdiv(self, device="cuda"):
+        """[2, F, nspec, 2]: vorticity fields, then divergence fields."""
+        import torch
+
+        return torch.empty((2, self.nfields, self.nspec, 2), dtype=self.dtype, device=device)
+
+    def empty_uv(self, device="cuda"):
+        """[2, F, npts]: U = u cos(lat) fields, then V = v cos(lat) fields."""
+        import torch
+
+        return torch.empty((2, self.nfields, self.npts), dtype=self.dtype, device=device)
+
+    def _vortdiv(self, t):
+        return self._ptr(t, 2 * self.nfields * self.nspec * 2, "vortdiv")
+
+    def _uv(self, t):
+        return self._ptr(t, 2 * self.nfields * self.npts, "uv")
+
     def _ws(self, t):
         import torch
 
@@ -313,6 +345,51 @@ class Plan:
             a, b = self._grid(x), self._spec(out)
         _check(self._lib.sht_transform_static(self._h, DIRECTIONS[direction], a, b, _stream_handle(stream)),
                "sht_transform_static")
+        return out
+
+    # ---- derivatives and vector transforms (vector plans) ----
+    def _run(self, fn, name, x, out, make_out, workspace, stream):
+        tmp = {}
+        if out is None:
+            tmp["out"] = make_out
+        if workspace is None:
+            tmp["ws"] = self.empty_workspace
+        t = self._temporaries(stream, x.device, **tmp) if tmp else {}
+        out = t.get("out", out)
+        workspace = t.get("ws", workspace)
+        a, b = fn(x, out)
+        _check(getattr(self._lib, name)(self._h, a, b, self._ws(workspace), _stream_handle(stream)), name)
+        return out
+
+    def vector_inverse(self, vortdiv, uv=None, workspace=None, stream=None):
+        """Winds [2, F, npts] (U, V) from vorticity and divergence [2, F, nspec, 2]."""
+        return self._run(lambda x, o: (self._vortdiv(x), self._uv(o)), "sht_vector_inverse", vortdiv, uv,
+                         self.empty_uv, workspace, stream)
+
+    def vector_direct(self, uv, vortdiv=None, workspace=None, stream=None):
+        """Vorticity and divergence [2, F, nspec, 2] from winds [2, F, npts]."""
+        return self._run(lambda x, o: (self._uv(x), self._vortdiv(o)), "sht_vector_direct", uv, vortdiv,
+                         self.empty_vortdiv, workspace, stream)
+
+    def gradient(self, spec, uv=None, workspace=None, stream=None):
+        """(df/dlambda, (1 - mu^2) df/dmu) [2, F, npts] of scalar fields [F, nspec, 2]."""
+        return self._run(lambda x, o: (self._spec(x), self._uv(o)), "sht_gradient", spec, uv, self.empty_uv,
+                         workspace, stream)
+
+    def spectral_op(self, op, x, out=None, stream=None):
+        """``dlambda`` | ``laplacian`` | ``inv_laplacian`` on spectral fields
+        [..., nspec, 2] of the plan's truncation (out may be x)."""
+        import torch
+
+        count = x.numel() // (self.nspec * 2)
+        if count * self.nspec * 2 != x.numel():
+            raise ValueError("x must hold whole spectral fields")
+        if out is None:
+            with torch.cuda.stream(stream if stream is not None else torch.cuda.current_stream()):
+                out = torch.empty_like(x)
+        a = self._ptr(x, count * self.nspec * 2, "x")
+        b = self._ptr(out, count * self.nspec * 2, "out")
+        _check(self._lib.sht_spectral_op(self._h, OPS[op], count, a, b, _stream_handle(stream)), "sht_spectral_op")
         return out
 
     def legendre_inverse(self, spec, workspace, stream=None):
