@@ -16,8 +16,13 @@ on the same GPU, and the FP64 CPU oracle's rate on a bounded sample).
     python bench.py [--steps K] [--warmup W] [--precision fp32|bf16x3|fp64]
                     [--variants bf16x3,fp64]
 
-The main precision is timed over K steps; each variant (other precisions of
-the same workload, for comparison) over min(K, 3) steps.
+The main precision and each variant (other precisions of the same workload,
+for comparison) are timed over K steps.  Further objects on the same line:
+``configs`` (the T79 single-field per-call latency and the T399 x 411 FP64
+throughput), ``stepping`` (time steps of synthesis -> grid-point operation
+-> analysis -> spectral operation, uncaptured against HIP-graph replay),
+``vector`` (vorticity/divergence <-> winds at TCo1279), ``batch`` and
+``serving``.
 """
 
 import argparse
@@ -383,57 +388,192 @@ def fp64_form_error(res):
     return err
 
 
-def cpu_baseline(workload, seed=0):
-    """The FP64 oracle on the host cores on a bounded sample of the workload:
-    one field; synthesis restricted to a ring subset and analysis restricted
-    to a wavenumber subset, each timed at two subset sizes and extended
-    linearly (fixed cost + per-ring / per-wavenumber cost) to the full ring
-    and wavenumber counts."""
-    import oracle
-    from paper_1908_06096_amd.inputs import grid_noise, spectral_coefficients
-
+def host_description():
+    """nproc, CPU model and the BLAS library numpy uses on this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas, threads = "unknown", os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
 
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        info = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if info:
+            blas = f"{info[0].get('internal_api')} {info[0].get('version')}"
+            threads = int(info[0].get("num_threads", threads))
     except Exception:
-        threads = os.cpu_count() or 1
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model, "blas": blas, "blas_threads": threads}
+
+
+def cpu_baseline(workload, seed=0, stride=None):
+    """The FP64 oracle on the host cores, one field of the workload, on a
+    bounded sample: synthesis of every `stride`-th ring and analysis of every
+    `stride`-th wavenumber (each restricted call does the full work of its
+    rings / wavenumbers: Legendre sums, brute-force DFTs).  The sample's time
+    times the stride estimates the full single-field round trip (no fitted
+    model; uniform sampling of rings and wavenumbers)."""
+    import oracle
+    from paper_1908_06096_amd.inputs import grid_noise, spectral_coefficients
+
+    host = host_description()
     N, grid, _F = WORKLOADS[workload]
+    if stride is None:
+        stride = 64 if N > 500 else 1
     geo = oracle.grid_geometry(N, grid)
+    t0 = time.perf_counter()
     gauss = oracle.gauss_newton(geo["nlat"])
+    t_gauss = time.perf_counter() - t0
     s = spectral_coefficients(N, 1, seed=seed)
     spec_c = s[..., 0] + 1j * s[..., 1]
     g = grid_noise(geo["npts"], 1, seed=seed)
-
-    def t_inverse(k):
-        rings = np.linspace(0, geo["nlat"] - 1, k).astype(int)
-        t0 = time.perf_counter()
-        oracle.inverse(spec_c, N, grid, rings=rings, geometry=geo, gauss=gauss)
-        return time.perf_counter() - t0
-
-    def t_direct(k):
-        ms = np.linspace(0, N, k).astype(int)
-        t0 = time.perf_counter()
-        oracle.direct(g, N, grid, ms=ms, geometry=geo, gauss=gauss)
-        return time.perf_counter() - t0
-
-    k1, k2 = (8, 16) if N > 500 else (4, 8)
-    i1, i2 = t_inverse(k1), t_inverse(k2)
-    d1, d2 = t_direct(k1), t_direct(k2)
-    bi = max((i2 - i1) / (k2 - k1), 0.0)
-    bd = max((d2 - d1) / (k2 - k1), 0.0)
-    inv_full = max(i1 - k1 * bi, 0.0) + geo["nlat"] * bi
-    dir_full = max(d1 - k1 * bd, 0.0) + (N + 1) * bd
-    value = 2.0 / (inv_full + dir_full)
-    return {
+    rings = np.arange(0, geo["nlat"], stride)
+    ms = np.arange(0, N + 1, stride)
+    t0 = time.perf_counter()
+    oracle.inverse(spec_c, N, grid, rings=rings, geometry=geo, gauss=gauss)
+    t_inv = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.direct(g, N, grid, ms=ms, geometry=geo, gauss=gauss)
+    t_dir = time.perf_counter() - t0
+    inv_full = t_inv * geo["nlat"] / rings.size
+    dir_full = t_dir * (N + 1) / ms.size
+    value = 2.0 / (inv_full + dir_full + t_gauss)
+    out = {
         "value": value,
         "unit": "field-transforms/s",
-        "cores": int(threads),
+        "cores": int(host["blas_threads"]),
         "kind": "oracle",
-        "sample": (f"{workload}, 1 field: FP64 oracle synthesis on {k1} and {k2} evenly spaced rings and analysis "
-                   f"on {k1} and {k2} evenly spaced wavenumbers ({i1 + i2 + d1 + d2:.1f} s measured), extended "
-                   f"linearly to {geo['nlat']} rings ({inv_full:.1f} s) and {N + 1} wavenumbers ({dir_full:.1f} s)"),
+        "sample": (f"{workload}, 1 field, FP64 oracle: synthesis of every {stride}th ring ({rings.size} of "
+                   f"{geo['nlat']}, {t_inv:.1f} s) and analysis of every {stride}th wavenumber ({ms.size} of "
+                   f"{N + 1}, {t_dir:.1f} s), each scaled by its sampling ratio, plus the latitudes "
+                   f"({t_gauss:.1f} s): {inv_full + dir_full + t_gauss:.1f} s per single-field round trip"),
     }
+    out.update({k: v for k, v in host.items() if k != "blas_threads"})
+    return out
+
+
+def time_calls(fn, n, stream):
+    """Mean ms of `fn()` over n back-to-back calls on `stream` (HIP events)."""
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def run_stepping(workload, precision, nsteps):
+    """Time steps (synthesis, logistic term on the grid, analysis, implicit
+    diffusion) on resident data: enqueued kernel by kernel, and replayed
+    from a HIP graph captured once."""
+    import torch
+
+    from paper_1908_06096_amd import sht
+
+    N, grid, F = WORKLOADS[workload]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    stream = torch.cuda.Stream()
+    out = {"workload": workload, "precision": precision, "steps": nsteps,
+           "step": "synthesis, g += dt r g (1 - g), analysis, a /= 1 + dt nu n(n+1)"}
+    with sht.Plan(N, grid, F, precision, stream=stream) as plan:
+        a = 0.05 * host_inputs(workload)
+        a[:, 0, 0] = 0.5 * np.sqrt(2.0)
+        gs = 10 if nsteps >= 100 else 1
+        runs = [("eager_us_per_step", False, 1), ("graph_us_per_step", True, 1)]
+        if gs > 1:
+            runs.append((f"graph{gs}_us_per_step", True, gs))
+        for key, graph, steps_per_graph in runs:
+            spec = torch.from_numpy(a).to(device="cuda", dtype=dt)
+            with sht.Stepper(plan, spec, 0.1, 1.0, 1e-2, graph=graph, graph_steps=steps_per_graph,
+                             stream=stream) as st:
+                ms = time_calls(lambda: st.run(steps_per_graph, stream=stream), nsteps // steps_per_graph, stream)
+            out[key] = ms * 1e3 / steps_per_graph
+    out["graph_speedup"] = out["eager_us_per_step"] / min(v for k, v in out.items() if k.startswith("graph")
+                                                          and k.endswith("_us_per_step"))
+    log(f"[bench] stepping {workload} {precision}: " +
+        ", ".join(f"{k} {v:.1f}" for k, v in out.items() if k.endswith("_us_per_step")))
+    return out
+
+
+def run_small_configs(steps):
+    """T79 full grid, one field, FP64: microseconds per call (a latency, not
+    a roofline case); T399 full grid x 411 fields, FP64: throughput."""
+    import torch
+
+    from paper_1908_06096_amd import sht
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    N, grid, F = WORKLOADS["T79-full-80x160-F1"]
+    with sht.Plan(N, grid, F, "fp64") as plan:
+        spec = torch.from_numpy(host_inputs("T79-full-80x160-F1")).cuda()
+        g = plan.empty_grid()
+        back = plan.empty_spec()
+        ws = plan.empty_workspace()
+        inv = time_calls(lambda: plan.inverse(spec, g, ws), 500, stream)
+        dirm = time_calls(lambda: plan.direct(g, back, ws), 500, stream)
+        torch.cuda.synchronize()
+        a = spec.clone()
+        a[:, : N + 1, 1] = 0
+        rt = float(torch.linalg.vector_norm(back - a) / torch.linalg.vector_norm(a))
+    out["T79-full-80x160-F1"] = {"precision": "fp64", "inverse_us_per_call": inv * 1e3,
+                                 "direct_us_per_call": dirm * 1e3, "round_trip_rel_l2": rt,
+                                 "field_transforms_per_s": 2.0 / ((inv + dirm) * 1e-3)}
+    log(f"[bench] T79 x 1 FP64: inverse {inv * 1e3:.1f} us, direct {dirm * 1e3:.1f} us per call")
+    torch.cuda.empty_cache()
+    r = run_gpu("T399-full-400x800-F411", "fp64", steps, 1)
+    geo = geometry_counts(r["N"], r["grid"])
+    st, rf = stage_report(r["N"], geo, r["F"], "fp64", r["per_stage_ms"])
+    out["T399-full-400x800-F411"] = {"precision": "fp64", "steps": steps,
+                                     "ms_per_step": r["total_ms"] / steps,
+                                     "value": 2.0 * r["F"] * steps / (r["total_ms"] * 1e-3),
+                                     "roofline": rf, "stages": st, "round_trip_rel_l2": r["round_trip_rel_l2"]}
+    r["plan"].close()
+    return out
+
+
+def run_vector(steps, workload="TCo1279-O1280-F411", precision="fp32", vfields=137):
+    """Vorticity and divergence of `vfields` vector fields (one wind per
+    level) -> winds U, V -> vorticity and divergence, at the workload's
+    truncation and grid.  Counts 2 components per vector field and
+    direction as field-transforms."""
+    import torch
+
+    from paper_1908_06096_amd import sht
+    from paper_1908_06096_amd.inputs import spectral_coefficients
+
+    N, grid, _F = WORKLOADS[workload]
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    stream = torch.cuda.current_stream()
+    with sht.Plan(N, grid, vfields, precision, vector=True) as plan:
+        d = 4
+        a = spectral_coefficients(N, 2 * d, seed=5)
+        idx = np.arange(2 * vfields) % (2 * d)
+        vd = torch.from_numpy(np.ascontiguousarray(a[idx])).to(device="cuda", dtype=dt).view(2, vfields, -1, 2)
+        uv = plan.empty_uv()
+        back = plan.empty_vortdiv()
+        ws = plan.empty_workspace()
+        inv = time_calls(lambda: plan.vector_inverse(vd, uv, ws), steps, stream)
+        dirm = time_calls(lambda: plan.vector_direct(uv, back, ws), steps, stream)
+        tab = plan.info.table_bytes
+    out = {"workload": f"{workload.split('-F')[0]}-V{vfields}", "precision": precision, "vector_fields": vfields,
+           "inverse_ms": inv, "direct_ms": dirm,
+           "value": 2.0 * 2 * vfields / ((inv + dirm) * 1e-3), "unit": "field-transforms/s (2 per vector field)",
+           "table_gb": tab / 1e9}
+    log(f"[bench] vector {out['workload']}: inverse {inv:.2f} ms, direct {dirm:.2f} ms")
+    return out
 
 
 def main():
@@ -448,6 +588,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-workload measurement")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the small configs, the time-stepping and the vector measurements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB first (reference for PMC byte counters)")
     ap.add_argument("--no-fp64-check", "--no-oracle-check", dest="no_fp64_check", action="store_true",
@@ -506,7 +648,7 @@ def main():
         import torch
 
         torch.cuda.empty_cache()
-        r = run_gpu(args.workload, prec, min(args.steps, 3), 1)
+        r = run_gpu(args.workload, prec, args.steps, 1)
         st, rf = stage_report(N, geo, F, prec, r["per_stage_ms"])
         variants[prec] = {
             "value": 2.0 * F * r["steps"] / (r["total_ms"] * 1e-3),
@@ -522,6 +664,16 @@ def main():
         del r
     if variants:
         out["variants"] = variants
+    if not args.no_extras:
+        import torch
+
+        torch.cuda.empty_cache()
+        out["configs"] = run_small_configs(args.steps)
+        torch.cuda.empty_cache()
+        out["stepping"] = [run_stepping("T79-full-80x160-F1", "fp64", 1000),
+                           run_stepping(args.workload, args.precision, min(args.steps, 5))]
+        torch.cuda.empty_cache()
+        out["vector"] = run_vector(min(args.steps, 5))
     if not args.no_batch:
         import torch
 

@@ -281,6 +281,38 @@ int sht_gradient(sht_plan_t plan, const void* spec, void* uv, void* workspace, v
  * truncation and data type; in == out is allowed.  Asynchronous. */
 int sht_spectral_op(sht_plan_t plan, int op, int count, const void* in, void* out, void* hip_stream);
 
+/* ---- Time stepping ----
+ *
+ * The loop a spectral model runs (report sections 4.2.2-4.2.3: synthesis,
+ * grid-point computations and analysis every time step, with every array
+ * allocated once outside the loop), here for the reaction-diffusion
+ * equation du/dt = nu Lap u + r u (1 - u) on the unit sphere, by
+ * semi-implicit Euler steps of length dt: the logistic term explicit on the
+ * grid, the diffusion implicit in spectral space,
+ *   g = synthesis(a);  g <- g + dt r g (1 - g);  b = analysis(g);
+ *   a_n^m <- b_n^m / (1 + dt nu n (n + 1)).
+ * A stepper binds a scalar plan to the state `spec` ([F][nspec], updated in
+ * place every step), a grid and a workspace (scratch).  With SHT_STEP_GRAPH
+ * `graph_steps` consecutive steps are captured once into a HIP graph on
+ * `hip_stream` (which must not be NULL) and replayed: one launch per
+ * graph_steps steps instead of one per kernel.  The buffers must outlive
+ * the stepper. */
+typedef struct sht_stepper_s* sht_stepper_t;
+enum sht_step_flags { SHT_STEP_GRAPH = 1 };
+
+/* dt >= 0, nu >= 0, all finite; 1 <= graph_steps <= 4096 (ignored
+ * without SHT_STEP_GRAPH).  Captures (no kernel runs) when SHT_STEP_GRAPH
+ * is set. */
+int sht_stepper_create(sht_stepper_t* out, sht_plan_t plan, double dt, double rate, double nu, void* spec,
+                       void* grid, void* workspace, int flags, int graph_steps, void* hip_stream);
+
+/* Enqueue `nsteps` time steps on `hip_stream` (asynchronous): nsteps /
+ * graph_steps graph replays, then the remaining steps kernel by kernel. */
+int sht_stepper_run(sht_stepper_t stepper, int nsteps, void* hip_stream);
+
+/* Release a stepper (synchronises the device first if it holds a graph). */
+int sht_stepper_destroy(sht_stepper_t stepper);
+
 /* Stage 1 of synthesis: per m, S_m = Pbar_even a_even and A_m = Pbar_odd
  * a_odd over the north rings carrying m, then c(ring j) = S + A and
  * c(mirror ring) = S - A, written in the synthesis form of the Fourier

@@ -5,6 +5,7 @@
 // or copies metadata happens once at plan (or batch) creation; the transform
 // calls only enqueue kernels.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -1408,6 +1409,120 @@ int sht_batch_destroy(sht_batch_t b) {
     if (e != hipSuccess) rc = hip_fail(e);
   }
   delete b;
+  return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Time stepping
+// ---------------------------------------------------------------------------
+
+struct sht_stepper_s {
+  sht_plan_t plan = nullptr;
+  void* spec = nullptr;
+  void* grid = nullptr;
+  void* ws = nullptr;
+  double dt = 0, rate = 0, nu = 0;
+  int graph_steps = 1;  // steps captured in one graph
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+// One time step on the stepper's buffers: synthesis, the logistic term on
+// the grid, analysis, implicit diffusion.
+int enqueue_step(const sht_stepper_s* st, hipStream_t s) {
+  sht_plan_t p = st->plan;
+  int rc = stage_legendre_inverse(p, st->spec, st->ws, s);
+  if (rc == SHT_OK) rc = stage_fourier_synthesis(p, st->ws, st->grid, s);
+  if (rc != SHT_OK) return rc;
+  HIP_TRY(launch_logistic(p->prec, (int64_t)p->F * p->npts, st->dt * st->rate, st->grid, s));
+  rc = stage_fourier_analysis(p, st->grid, st->ws, s);
+  if (rc == SHT_OK) rc = stage_legendre_direct(p, st->ws, st->spec, s);
+  if (rc != SHT_OK) return rc;
+  HIP_TRY(launch_implicit_diffusion(p->prec, p->N, p->F, st->dt * st->nu, st->spec, s));
+  return SHT_OK;
+}
+
+// Capture graph_steps steps into one graph on stream `s` (which must not be
+// the null stream).
+int capture_step(sht_stepper_s* st, hipStream_t s) {
+  HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  int rc = SHT_OK;
+  for (int i = 0; i < st->graph_steps && rc == SHT_OK; ++i) rc = enqueue_step(st, s);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(s, &g);
+  if (rc != SHT_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  const hipError_t ei = hipGraphInstantiate(&st->exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    st->exec = nullptr;
+    return hip_fail(ei);
+  }
+  return SHT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sht_stepper_create(sht_stepper_t* out, sht_plan_t plan, double dt, double rate, double nu, void* spec,
+                       void* grid, void* workspace, int flags, int graph_steps, void* hip_stream) {
+  if (!out) return SHT_EINVAL;
+  *out = nullptr;
+  if (!scalar_plan(plan) || !spec || !grid || !workspace || (flags & ~SHT_STEP_GRAPH)) return SHT_EINVAL;
+  if (graph_steps < 1 || graph_steps > 4096) return SHT_EINVAL;
+  if (!(dt >= 0.0) || !(nu >= 0.0) || !std::isfinite(rate) || !std::isfinite(dt) || !std::isfinite(nu))
+    return SHT_EINVAL;
+  if ((flags & SHT_STEP_GRAPH) && !hip_stream) return SHT_EINVAL;  // the null stream cannot be captured
+  sht_stepper_s* st = new (std::nothrow) sht_stepper_s();
+  if (!st) return SHT_ENOMEM;
+  st->plan = plan;
+  st->spec = spec;
+  st->grid = grid;
+  st->ws = workspace;
+  st->dt = dt;
+  st->rate = rate;
+  st->nu = nu;
+  st->graph_steps = (flags & SHT_STEP_GRAPH) ? graph_steps : 1;
+  if (flags & SHT_STEP_GRAPH) {
+    const int rc = capture_step(st, (hipStream_t)hip_stream);
+    if (rc != SHT_OK) {
+      delete st;
+      return rc;
+    }
+  }
+  *out = st;
+  return SHT_OK;
+}
+
+int sht_stepper_run(sht_stepper_t st, int nsteps, void* hip_stream) {
+  if (!st || nsteps < 0) return SHT_EINVAL;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  int left = nsteps;
+  if (st->exec)
+    for (; left >= st->graph_steps; left -= st->graph_steps) HIP_TRY(hipGraphLaunch(st->exec, s));
+  for (; left > 0; --left) {
+    const int rc = enqueue_step(st, s);
+    if (rc != SHT_OK) return rc;
+  }
+  return SHT_OK;
+}
+
+int sht_stepper_destroy(sht_stepper_t st) {
+  if (!st) return SHT_EINVAL;
+  int rc = SHT_OK;
+  if (st->exec) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipGraphExecDestroy(st->exec);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  delete st;
   return rc;
 }
 

@@ -249,6 +249,10 @@ hipError_t launch_vortdiv_from_projections(int N, int F, int prec, const void* p
 hipError_t launch_spectral_op(int N, int count, int op, int prec, const void* in, void* out, hipStream_t s);
 hipError_t launch_analysis_weight(int nlat, const double* mu, const double* w, double* wa, hipStream_t s);
 
+// stepper.hip: the grid-point and spectral operations of the time step.
+hipError_t launch_logistic(int prec, int64_t n, double a, void* grid, hipStream_t s);
+hipError_t launch_implicit_diffusion(int prec, int N, int F, double c, void* spec, hipStream_t s);
+
 // fft.hip.  Same launch model, one launch per tier: the items of one launch
 // all belong to classes of that tier.
 hipError_t launch_fourier_synthesis(const DevPlan* plans, int prec, int tier, const FftItem* items, int nitems,

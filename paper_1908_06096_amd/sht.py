@@ -11,7 +11,7 @@ import os
 
 import numpy as np
 
-__all__ = ["Plan", "Batch", "SHTError", "library", "LIB_PATH", "GRIDS", "PRECISIONS", "TILES", "exported_symbols"]
+__all__ = ["Plan", "Batch", "Stepper", "SHTError", "library", "LIB_PATH", "GRIDS", "PRECISIONS", "TILES", "exported_symbols"]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libshtmi.so")
 GRIDS = {"full": 0, "octahedral": 1}
@@ -85,6 +85,11 @@ _SIGNATURES = {
     "sht_gradient": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "sht_spectral_op": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p]),
+    "sht_stepper_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_double,
+                                          ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "sht_stepper_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "sht_stepper_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sht_transform_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_void_p]),
     "sht_strerror": (ctypes.c_char_p, [ctypes.c_int]),
@@ -487,6 +492,52 @@ class Batch:
     def close(self):
         if self._h:
             _check(self._lib.sht_batch_destroy(self._h), "sht_batch_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+class Stepper:
+    """Time steps of du/dt = nu Lap u + r u (1 - u) on the unit sphere
+    (semi-implicit Euler: logistic term on the grid, implicit diffusion in
+    spectral space) on a scalar plan.  ``spec`` [F, nspec, 2] is the state,
+    updated in place by ``run``; ``graph=True`` captures ``graph_steps``
+    steps into a HIP graph (on ``stream``, which must not be the null
+    stream) and replays it."""
+
+    def __init__(self, plan, spec, dt, rate, nu, graph=False, graph_steps=1, grid=None, workspace=None,
+                 stream=None):
+        import torch
+
+        self._lib = plan._lib
+        self.plan = plan
+        st = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(st):
+            self.grid = plan.empty_grid() if grid is None else grid
+            self.workspace = plan.empty_workspace() if workspace is None else workspace
+        self.spec = spec
+        self._h = ctypes.c_void_p()
+        _check(self._lib.sht_stepper_create(ctypes.byref(self._h), plan._h, float(dt), float(rate), float(nu),
+                                            plan._spec(spec), plan._grid(self.grid), plan._ws(self.workspace),
+                                            1 if graph else 0, int(graph_steps), _stream_handle(st)),
+               "sht_stepper_create")
+
+    def run(self, nsteps, stream=None):
+        _check(self._lib.sht_stepper_run(self._h, int(nsteps), _stream_handle(stream)), "sht_stepper_run")
+
+    def close(self):
+        if self._h:
+            _check(self._lib.sht_stepper_destroy(self._h), "sht_stepper_destroy")
             self._h = ctypes.c_void_p()
 
     def __del__(self):

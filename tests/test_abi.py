@@ -65,3 +65,10 @@ def test_null_handles_rejected():
     assert lib.sht_direct(None, None, None, None, None) == -1
     assert lib.sht_workspace_size(None) == 0
     assert lib.sht_transform_static(None, 0, None, None, None) == -1
+    assert lib.sht_stepper_create(None, None, 0.1, 1.0, 0.0, None, None, None, 0, 1, None) == -1
+    assert lib.sht_stepper_run(None, 1, None) == -1
+    assert lib.sht_stepper_destroy(None) == -1
+    assert lib.sht_vector_inverse(None, None, None, None, None) == -1
+    assert lib.sht_vector_direct(None, None, None, None, None) == -1
+    assert lib.sht_gradient(None, None, None, None, None) == -1
+    assert lib.sht_spectral_op(None, 0, 1, None, None, None) == -1
