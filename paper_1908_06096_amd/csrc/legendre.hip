@@ -711,6 +711,206 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
   __syncthreads();
 }
 
+// Synthesis in BF16 split precision on a wide tile: 256 rings x 128 real
+// columns, both parities, eight waves (512 threads, one work group per CU),
+// MFMA 32x32x16.  A step takes 16 k of each parity (32 consecutive n):
+// 32 KB of table and 16 KB of spectral operand move into LDS for 192 MFMAs,
+// twice the flops per byte of the 128 x 64 tile, and both stages are double
+// buffered (96 KB), so one barrier per step separates the copies of step
+// k + 1 from the products of step k.  Wave w owns rows 64 (w >> 1) and
+// columns 64 (w & 1) of both parities (2 x 2 blocks of 32 x 32 each), so
+// the N/S fold (S + A, S - A) happens in its registers.
+//
+// MFMA 32x32x16 bf16 operand placement, lane l: A[row l % 32][k 8 (l / 32)
+// + i], B[k 8 (l / 32) + i][col l % 32] (i < 8, one 16-byte operand);
+// accumulator element e holds D[8 (e / 4) + 4 (l / 32) + e % 4][l % 32].
+//
+// LDS stage layout, 16-byte units of 8 consecutive k:
+//   table     [parity][plane][k chunk (2)][row (256)]
+//   spectral  [parity][plane][k chunk (2)][column (128) ^ chunk]
+// (the spectral column is XORed with the chunk so that the two chunks'
+// staging writes, which the lanes of one field make 4 bytes apart, fall on
+// different banks; the operand reads keep 32 consecutive units per chunk).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ inline f32x16 mfma32_bf16(const uint4& a, const uint4& b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                 0, 0, 0);
+}
+
+constexpr int BW_BM = 256, BW_BN = 128, BW_KI = 16;
+
+__device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const WorkItem it,
+                                                         const float* __restrict__ spec, float* __restrict__ four) {
+  constexpr int BM = BW_BM, BN = BW_BN, KI = BW_KI;
+  constexpr int NCK = KI / KCH;         // k chunks per parity per step (2)
+  constexpr int AS = 2 * 2 * NCK * BM;  // 16-byte units of one table stage
+  constexpr int BS = 2 * 2 * NCK * BN;  // 16-byte units of one spectral stage
+  static_assert(NCK == 2 && BM == 256 && BN == 128, "tile shape");
+  __shared__ __align__(16) uint4 smem[2 * AS + 2 * BS];  // 96 KB
+
+  const MInfo mi = gload(p.ms + it.m);
+  const int m = mi.m;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int rq = wave >> 1, cq = wave & 1;
+  const int kpmax = mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1];
+  const int nk = (kpmax + KI - 1) / KI;
+
+  // Table copies: wave w fills (parity, plane) = w / 2, chunk w % 2 of a
+  // stage, four 64-row groups of 1 KB (64 lanes x 16 bytes, contiguous in
+  // the chunk-major table).  Reads past the table's padded k range return
+  // zero; rows past Lp read the next chunk's rows and only feed rows past L,
+  // whose outputs are never stored.
+  const u16* tab = (const u16*)p.tab;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int cpar = wv >> 2, cpl = (wv >> 1) & 1, cch = wv & 1;
+  // (selects rather than indexing mi.toff / mi.Kp with a variable, which
+  // would put a copy of mi in memory)
+  const int64_t ctoff = cpar ? mi.toff[1] : mi.toff[0];
+  const int ckp = cpar ? mi.Kp[1] : mi.Kp[0];
+  const __amdgpu_buffer_rsrc_t tr =
+      buffer_rsrc_uniform(tab + (cpl ? p.tab_plane : 0) + ctoff, (uint64_t)ckp * mi.Lp * 2);
+  const uint32_t a_step = __builtin_amdgcn_readfirstlane((uint32_t)NCK * mi.Lp * KCH * 2);
+  const uint32_t t_lane = ((uint32_t)(it.t0 + lane) + (uint32_t)cch * mi.Lp) * KCH * 2;
+  auto fetch_table = [&](int kc, int stage) {
+    const uint32_t sa = (uint32_t)kc * a_step;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      SHT_LDS void* dst = (SHT_LDS void*)(smem + stage * AS + ((cpar * 2 + cpl) * NCK + cch) * BM + 64 * g);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(tr, dst, 16, t_lane + (uint32_t)(64 * g) * KCH * 2, sa, 0, 0);
+    }
+  };
+  // Spectral values: thread (fi, sg) loads n - m = 32 kc + 4 sg .. + 3 of
+  // field f0 + fi (32 bytes); the field index is clamped to F - 1 (fields
+  // past F only feed outputs never stored) and values read past n = N meet
+  // zero table entries.
+  const int fi = tid >> 3, sg = tid & 7;
+  const int f0 = it.c0 / 2;
+  const int f = f0 + fi;
+  const uint32_t fl = (uint32_t)((f < p.F ? f : p.F - 1) - f0);
+  const int64_t sbase = (int64_t)f0 * p.nspec + mi.spec_off;
+  const __amdgpu_buffer_rsrc_t sr =
+      buffer_rsrc_uniform((const float2*)spec + sbase, (uint64_t)((int64_t)p.F * p.nspec - sbase) * 8u);
+  const uint32_t b_off = (fl * (uint32_t)p.nspec + 4u * sg) * 8u;
+  const bool m0 = m == 0;
+  float4 rv[2];
+  auto fetch_spec = [&](int kc) {
+    const uint32_t sb = (uint32_t)kc * (2 * KI * 8);
+    rv[0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off, sb, 0));
+    rv[1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off + 16, sb, 0));
+  };
+
+  f32x16 acc[2][2][2];
+#pragma unroll
+  for (int pa = 0; pa < 2; ++pa)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[pa][i][j] = f32x16{};
+
+  fetch_table(0, 0);
+  fetch_spec(0);
+  for (int kc = 0; kc < nk; ++kc) {
+    const int st = kc & 1;
+    uint4* Bs = smem + 2 * AS + st * BS;
+    // n - m = 4 sg + q (q < 4): parity q & 1, k = 2 sg + (q >> 1) within the
+    // step, i.e. chunk sg >> 2, bytes 4 (sg & 3) of the unit; Im a_n^0 dropped
+    {
+      const int ch = sg >> 2;
+#pragma unroll
+      for (int pa = 0; pa < 2; ++pa) {
+#pragma unroll
+        for (int comp = 0; comp < 2; ++comp) {
+          const float x0 = pa ? (comp ? rv[0].w : rv[0].z) : (comp ? rv[0].y : rv[0].x);
+          const float x1 = pa ? (comp ? rv[1].w : rv[1].z) : (comp ? rv[1].y : rv[1].x);
+          uint32_t h, l;
+          split2_bf16((comp && m0) ? 0.f : x0, (comp && m0) ? 0.f : x1, &h, &l);
+          const int col = (2 * fi + comp) ^ ch;
+          uint32_t* dh = (uint32_t*)(Bs + ((pa * 2 + 0) * NCK + ch) * BN + col) + (sg & 3);
+          uint32_t* dl = (uint32_t*)(Bs + ((pa * 2 + 1) * NCK + ch) * BN + col) + (sg & 3);
+          *dh = h;
+          *dl = l;
+        }
+      }
+    }
+    // this step's table copies (issued a step ago) have landed in every wave,
+    // and every wave's spectral staging is visible
+    __syncthreads();
+    if (kc + 1 < nk) {
+      fetch_table(kc + 1, st ^ 1);
+      fetch_spec(kc + 1);
+    }
+    const uint4* As = smem + st * AS;
+    const int ch = lane >> 5;
+#pragma unroll
+    for (int pa = 0; pa < 2; ++pa) {
+      uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = 64 * rq + 32 * i + (lane & 31);
+        ah[i] = As[((pa * 2 + 0) * NCK + ch) * BM + r];
+        al[i] = As[((pa * 2 + 1) * NCK + ch) * BM + r];
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = (64 * cq + 32 * j + (lane & 31)) ^ ch;
+        bh[j] = Bs[((pa * 2 + 0) * NCK + ch) * BN + c];
+        bl[j] = Bs[((pa * 2 + 1) * NCK + ch) * BN + c];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[pa][i][j] = mfma32_bf16(al[i], bh[j], acc[pa][i][j]);
+          acc[pa][i][j] = mfma32_bf16(ah[i], bl[j], acc[pa][i][j]);
+          acc[pa][i][j] = mfma32_bf16(ah[i], bh[j], acc[pa][i][j]);
+        }
+    }
+  }
+  __syncthreads();
+
+  // epilogue: Fourier row offsets of the tile's rings and their mirrors
+  // through LDS, then north = S + A and south = S - A from the registers
+  int64_t* roff = (int64_t*)smem;  // [256][2]
+  const int64_t rowlen = 2 * (int64_t)p.Fp;
+  if (tid < BM) {
+    const int row = it.t0 + tid;
+    int64_t on = 0, os = 0;
+    if (row < mi.L) {
+      const RingInfo rn = gload(p.rings + mi.first_ring + row);
+      on = (rn.frow + m) * rowlen;
+      os = (gload(p.rings + rn.mirror).frow + m) * rowlen;
+    }
+    roff[2 * tid] = on;
+    roff[2 * tid + 1] = os;
+  }
+  __syncthreads();
+  const int twoF = 2 * p.F;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int rl = 64 * rq + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+      if (it.t0 + rl >= mi.L) continue;
+      float* dn = four + roff[2 * rl];
+      float* ds = four + roff[2 * rl + 1];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int col = it.c0 + 64 * cq + 32 * j + (lane & 31);
+        if (col < twoF) {
+          const float S = acc[0][i][j][e];
+          const float A = acc[1][i][j][e];
+          gstore(dn + col, S + A);
+          gstore(ds + col, S - A);
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Analysis in BF16 split precision: out^T[c][k] = sum_j X^T[c][j] T[j][k]
 // with K = rings.  Both operands need the rings contiguous per lane, so the
 // Fourier rows are gathered 8 rings at a time per column and the table
@@ -945,6 +1145,19 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_bf16x3_kernel(const D
   }
 }
 
+__global__ __launch_bounds__(512, 1) void legendre_inverse_bf16x3_wide_kernel(const DevPlan* __restrict__ plans,
+                                                                           const WorkItem* __restrict__ items,
+                                                                           int nitems, const IoBind* __restrict__ io,
+                                                                           IoBind io0) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const WorkItem it = gload(items + w);
+    if (it.m < 0) continue;  // empty slot of the work list
+    const DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
+    inverse_bf16x3_wide_tile(p, it, (const float*)b.spec, (float*)b.ws);
+  }
+}
+
 template <int BC, int BK>
 __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const DevPlan* __restrict__ plans,
                                                                      const WorkItem* __restrict__ items, int nitems,
@@ -969,6 +1182,7 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const De
 #define INV_F32_C64 legendre_inverse_kernel<float, 128, 64, 16, 2>
 #define INV_F32_C32 legendre_inverse_kernel<float, 128, 32, 16, 1>
 #define INV_BF16 legendre_inverse_bf16x3_kernel
+#define INV_BF16_WIDE legendre_inverse_bf16x3_wide_kernel
 #define DIR_F64_C64 legendre_direct_kernel<double, 64, 64, 16, 2>
 #define DIR_F64_C32 legendre_direct_kernel<double, 32, 64, 16, 4>
 #define DIR_F32_C128 legendre_direct_kernel<float, 128, 64, 16, 2>
@@ -979,13 +1193,15 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const De
 bool legendre_variant_supported(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C64 || variant == TILE_C32;
   if (prec == SHT_FP32) return variant >= 0 && variant < NUM_TILE_VARIANTS;
-  return variant == TILE_C64;  // bf16x3: synthesis 128 x 64, analysis 64 k x 128 columns
+  // bf16x3: synthesis 128 x 64 (C64) or 256 x 128 (C128); analysis 64 k x 128 columns
+  return variant == TILE_C64 || variant == TILE_C128;
 }
 
 void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* dir_rows, int* dir_cols) {
   const int cols = variant == TILE_C128 ? 128 : variant == TILE_C64 ? 64 : 32;
   *inv_rows = (prec == SHT_FP64) ? 64 : 128;
   *inv_cols = cols;
+  if (prec == SHT_BF16X3 && variant == TILE_C128) *inv_rows = 256;
   *dir_rows = 64;
   *dir_cols = (prec == SHT_BF16X3) ? 128 : cols;
 }
@@ -999,8 +1215,10 @@ static const void* inverse_fn(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C32 ? fn(INV_F64_C32) : fn(INV_F64_C64);
   if (prec == SHT_FP32)
     return variant == TILE_C128 ? fn(INV_F32_C128) : variant == TILE_C64 ? fn(INV_F32_C64) : fn(INV_F32_C32);
-  return fn(INV_BF16);
+  return variant == TILE_C128 ? fn(INV_BF16_WIDE) : fn(INV_BF16);
 }
+
+static int inverse_threads(int prec, int variant) { return (prec == SHT_BF16X3 && variant == TILE_C128) ? 512 : 256; }
 
 static const void* direct_fn(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C32 ? fn(DIR_F64_C32) : fn(DIR_F64_C64);
@@ -1012,28 +1230,30 @@ static const void* direct_fn(int prec, int variant) {
 int legendre_blocks_per_cu(int prec, int variant, bool inverse) {
   int n = 0;
   const void* f = inverse ? inverse_fn(prec, variant) : direct_fn(prec, variant);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, 256, 0) != hipSuccess || n < 1) n = 1;
+  const int threads = inverse ? inverse_threads(prec, variant) : 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, 0) != hipSuccess || n < 1) n = 1;
   return n;
 }
 
-static hipError_t launch(const void* f, int grid_blocks, hipStream_t s, const DevPlan* plans, const WorkItem* items,
-                         int nitems, const IoBind* io, IoBind io0) {
+static hipError_t launch(const void* f, int threads, int grid_blocks, hipStream_t s, const DevPlan* plans,
+                         const WorkItem* items, int nitems, const IoBind* io, IoBind io0) {
   void* args[] = {(void*)&plans, (void*)&items, (void*)&nitems, (void*)&io, (void*)&io0};
-  return hipLaunchKernel(f, dim3(grid_blocks), dim3(256), args, 0, s);
+  return hipLaunchKernel(f, dim3(grid_blocks), dim3(threads), args, 0, s);
 }
 
 hipError_t launch_legendre_inverse(const DevPlan* plans, int prec, int variant, const WorkItem* items, int nitems,
                                    const IoBind* io, IoBind io0, int grid_blocks, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (!legendre_variant_supported(prec, variant)) return hipErrorInvalidValue;
-  return launch(inverse_fn(prec, variant), grid_blocks, s, plans, items, nitems, io, io0);
+  return launch(inverse_fn(prec, variant), inverse_threads(prec, variant), grid_blocks, s, plans, items, nitems, io,
+                io0);
 }
 
 hipError_t launch_legendre_direct(const DevPlan* plans, int prec, int variant, const WorkItem* items, int nitems,
                                   const IoBind* io, IoBind io0, int grid_blocks, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (!legendre_variant_supported(prec, variant)) return hipErrorInvalidValue;
-  return launch(direct_fn(prec, variant), grid_blocks, s, plans, items, nitems, io, io0);
+  return launch(direct_fn(prec, variant), 256, grid_blocks, s, plans, items, nitems, io, io0);
 }
 
 }  // namespace shtmi

@@ -50,6 +50,36 @@ def test_legendre_inverse(sht, case):
         assert rel_l2(got, four) <= TOL[prec]
 
 
+# bf16x3 synthesis with the 256 x 128 tile (eight waves, MFMA 32x32x16):
+# ragged row tiles (L not a multiple of 256), column tiles past 2F, one and
+# several k steps, m = 0
+WIDE = [(31, "full", 1), (47, "octahedral", 33), (95, "octahedral", 70), (159, "octahedral", 5),
+        (255, "octahedral", 64)]
+
+
+@pytest.mark.parametrize("case", WIDE, ids=lambda c: "T%d-%s-F%d" % c)
+def test_legendre_inverse_bf16x3_wide_tile(sht, case):
+    N, grid, F = case
+    with sht.Plan(N, grid, F, "bf16x3") as plan:
+        plan.set_tile("c128")
+        assert plan.tile == "c128"
+        spec_t, spec_c = spec_inputs(plan, seed=1)
+        ws = plan.empty_workspace()
+        print(f"bf16x3 wide synthesis T{N} {grid} F={F}", flush=True)
+        plan.legendre_inverse(spec_t, ws)
+        torch.cuda.synchronize()
+        got = plan.synthesis_fourier_view(ws)[:, :F].cpu().numpy().T
+        four, _g = oracle.inverse(spec_c, N, grid)
+        assert rel_l2(got, four) <= TOL["bf16x3"]
+        # the same coefficients through the 128 x 64 tile agree to the split's rounding
+        plan.set_tile("c64")
+        ws2 = plan.empty_workspace()
+        plan.legendre_inverse(spec_t, ws2)
+        torch.cuda.synchronize()
+        other = plan.synthesis_fourier_view(ws2)[:, :F].cpu().numpy().T
+        assert rel_l2(got, other) <= 1e-6
+
+
 @pytest.mark.parametrize("case", CASES, ids=_ids)
 def test_fourier_synthesis(sht, case):
     N, grid, F, prec = case
