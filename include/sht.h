@@ -172,6 +172,14 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
 /* Release a plan and its device memory (synchronises the device first). */
 int sht_plan_destroy(sht_plan_t plan);
 
+/* Release a plan in stream order, without synchronising: its device memory
+ * (and the shared tables, if this was the last plan holding them) is freed
+ * on `hip_stream` after the work enqueued there before the call.  The caller
+ * guarantees that no work on other streams still uses the plan (for example
+ * by waiting for an event of its last transform first).  For serving loops
+ * that must not stall every stream to drop one plan. */
+int sht_plan_destroy_async(sht_plan_t plan, void* hip_stream);
+
 /* Sizes of a plan (host struct, no device work). */
 int sht_plan_info(sht_plan_t plan, sht_info* out);
 

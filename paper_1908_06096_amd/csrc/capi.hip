@@ -182,13 +182,22 @@ int shtmi::hip_status(hipError_t e) {
 // Device tables of a (truncation, grid, precision): geometry metadata,
 // latitudes and weights, Pbar tables, FFT tables.  Shared by every plan made
 // from the same base plan; freed with the last of them.
+// The arenas are stream-ordered allocations (hipMallocAsync on the creating
+// stream), so that they can also be released in stream order
+// (sht_plan_destroy_async) without waiting for the whole device.
 struct SharedTables {
   void* arena = nullptr;
   size_t bytes = 0;
+  bool async = false;         // release in stream order on `release`
+  hipStream_t release = nullptr;
   ~SharedTables() {
-    if (arena) {
+    if (!arena) return;
+    if (async) {
+      (void)hipFreeAsync(arena, release);
+    } else {
       (void)hipDeviceSynchronize();
-      (void)hipFree(arena);
+      (void)hipFreeAsync(arena, nullptr);
+      (void)hipStreamSynchronize(nullptr);
     }
   }
 };
@@ -213,6 +222,7 @@ struct sht_plan_s {
   int syn_off[FFT_TIERS + 1] = {}, ana_off[FFT_TIERS + 1] = {};  // first work group of each tier
   int64_t tab_plane = 0;
   size_t tab_bytes = 0, fft_bytes = 0;
+  size_t inv_cap = 0, dir_cap = 0;  // work items the arena holds
   size_t lds_syn = 0, lds_ana = 0;            // largest of the tiers'
   size_t lds_syn_t[FFT_TIERS] = {}, lds_ana_t[FFT_TIERS] = {};
   int max_Lp = 0;
@@ -579,30 +589,19 @@ int build_host(sht_plan_s* p) {
   return SHT_OK;
 }
 
-// Capacity of the Legendre work lists: the largest list any tile variant
-// needs, so that sht_plan_set_tile can switch variants in place.
-void list_capacity(const sht_plan_s* p, size_t* inv_cap, size_t* dir_cap) {
-  *inv_cap = p->inv_items.size();
-  *dir_cap = p->dir_items.size();
-  for (int v = 0; v < NUM_TILE_VARIANTS; ++v) {
-    if (!legendre_variant_supported(p->prec, v)) continue;
-    std::vector<WorkItem> a, b;
-    legendre_items(p, v, 0, &a, &b);
-    *inv_cap = std::max(*inv_cap, a.size());
-    *dir_cap = std::max(*dir_cap, b.size());
-  }
-}
-
 // The plan's own arena: its descriptor and work lists (tables already set).
+// The Legendre lists get room for the variant in use; sht_plan_set_tile
+// makes a new arena when another variant needs more.
 int build_own(sht_plan_s* p, hipStream_t s) {
-  size_t inv_cap, dir_cap;
-  list_capacity(p, &inv_cap, &dir_cap);
+  const size_t inv_cap = p->inv_items.size(), dir_cap = p->dir_items.size();
+  p->inv_cap = inv_cap;
+  p->dir_cap = dir_cap;
   const size_t parts[6] = {sizeof(DevPlan), sizeof(WorkItem) * inv_cap, sizeof(WorkItem) * dir_cap,
                            sizeof(FftItem) * p->syn_items.size(), sizeof(FftItem) * p->ana_items.size(),
                            p->vec ? sizeof(DevPlan) : 0};
   size_t total = 0;
   for (size_t q : parts) total += align256(q);
-  if (hipMalloc(&p->arena, total) != hipSuccess) {
+  if (hipMallocAsync(&p->arena, total, s) != hipSuccess) {
     (void)hipGetLastError();
     p->arena = nullptr;
     return SHT_ENOMEM;
@@ -652,7 +651,7 @@ int build_device(sht_plan_s* p, hipStream_t s) {
   size_t total = 0;
   for (const Part& q : parts) total += align256(q.bytes);
   p->tables = std::make_shared<SharedTables>();
-  if (hipMalloc(&p->tables->arena, total) != hipSuccess) {
+  if (hipMallocAsync(&p->tables->arena, total, s) != hipSuccess) {
     (void)hipGetLastError();
     p->tables->arena = nullptr;
     return SHT_ENOMEM;
@@ -937,6 +936,15 @@ int batch_run(sht_batch_s* b, hipStream_t s, bool inverse) {
 
 namespace {
 
+// Free a plan's own arena after a failed creation (nothing of it is in use).
+void release_own(sht_plan_s* p) {
+  if (!p->arena) return;
+  (void)hipDeviceSynchronize();
+  (void)hipFreeAsync(p->arena, nullptr);
+  (void)hipStreamSynchronize(nullptr);
+  p->arena = nullptr;
+}
+
 int plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int precision, bool vec, void* hip_stream) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
@@ -956,10 +964,7 @@ int plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int prec
   int rc = build_host(p);
   if (rc == SHT_OK) rc = build_device(p, (hipStream_t)hip_stream);
   if (rc != SHT_OK) {
-    if (p->arena) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(p->arena);
-    }
+    release_own(p);
     delete p;  // releases the tables
     return rc;
   }
@@ -1042,7 +1047,7 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
     if (e != hipSuccess) rc = hip_fail(e);
   }
   if (rc != SHT_OK) {
-    if (p->arena) (void)hipFree(p->arena);
+    release_own(p);
     delete p;
     return rc;
   }
@@ -1055,10 +1060,28 @@ int sht_plan_destroy(sht_plan_t p) {
   int rc = SHT_OK;
   if (p->arena) {
     hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess) e = hipFree(p->arena);
+    if (e == hipSuccess) e = hipFreeAsync(p->arena, nullptr);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) rc = hip_fail(e);
   }
   delete p;  // the tables go with the last plan that shares them
+  return rc;
+}
+
+int sht_plan_destroy_async(sht_plan_t p, void* hip_stream) {
+  if (!p) return SHT_EINVAL;
+  int rc = SHT_OK;
+  const hipStream_t s = (hipStream_t)hip_stream;
+  if (p->arena) {
+    const hipError_t e = hipFreeAsync(p->arena, s);
+    if (e != hipSuccess) rc = hip_fail(e);
+  }
+  if (p->tables) {
+    // if this plan holds the last reference, the tables go in stream order too
+    p->tables->async = true;
+    p->tables->release = s;
+  }
+  delete p;
   return rc;
 }
 
@@ -1119,7 +1142,58 @@ int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
   if (!p || !legendre_variant_supported(p->prec, tile)) return SHT_EINVAL;
   std::vector<WorkItem> inv, dir;
   legendre_items(p, tile, 0, &inv, &dir);
-  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  const hipStream_t s = (hipStream_t)stream;
+  HIP_TRY(hipStreamSynchronize(s));
+  if (inv.size() > p->inv_cap || dir.size() > p->dir_cap) {
+    // a new arena with room for these lists (the plan may have run on other
+    // streams: wait for the device before the old one goes)
+    HIP_TRY(hipDeviceSynchronize());
+    sht_plan_s keep;  // what to restore if the new arena cannot be made
+    keep.arena = p->arena;
+    keep.inv_items.swap(p->inv_items);
+    keep.dir_items.swap(p->dir_items);
+    keep.variant = p->variant;
+    keep.inv_cap = p->inv_cap;
+    keep.dir_cap = p->dir_cap;
+    keep.d_self = p->d_self;
+    keep.d_inv = p->d_inv;
+    keep.d_dir = p->d_dir;
+    keep.d_syn = p->d_syn;
+    keep.d_ana = p->d_ana;
+    keep.d_self_h = p->d_self_h;
+    void* old = p->arena;
+    p->arena = nullptr;
+    p->inv_items = inv;
+    p->dir_items = dir;
+    p->variant = tile;
+    const int rc = build_own(p, s);
+    if (rc != SHT_OK) {
+      if (p->arena) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFreeAsync(p->arena, s);
+        (void)hipStreamSynchronize(s);
+      }
+      p->arena = keep.arena;
+      p->inv_items.swap(keep.inv_items);
+      p->dir_items.swap(keep.dir_items);
+      p->variant = keep.variant;
+      p->inv_cap = keep.inv_cap;
+      p->dir_cap = keep.dir_cap;
+      p->d_self = keep.d_self;
+      p->d_inv = keep.d_inv;
+      p->d_dir = keep.d_dir;
+      p->d_syn = keep.d_syn;
+      p->d_ana = keep.d_ana;
+      p->d_self_h = keep.d_self_h;
+      keep.arena = nullptr;
+      return rc;
+    }
+    keep.arena = nullptr;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipFreeAsync(old, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return SHT_OK;
+  }
   HIP_TRY(hipMemcpy(p->d_inv, inv.data(), sizeof(WorkItem) * inv.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->d_dir, dir.data(), sizeof(WorkItem) * dir.size(), hipMemcpyHostToDevice));
   p->inv_items = inv;

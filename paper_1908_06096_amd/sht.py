@@ -56,6 +56,7 @@ _SIGNATURES = {
     "sht_plan_create_like": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_void_p]),
     "sht_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sht_plan_destroy_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sht_plan_info": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(SHTInfo)]),
     "sht_plan_geometry": (ctypes.c_int, [ctypes.c_void_p, _c_dbl_p, _c_dbl_p, _c_int_p, _c_int_p, _c_i64_p,
                                          _c_i64_p]),
@@ -179,6 +180,13 @@ class Plan:
     def close(self):
         if self._h:
             _check(self._lib.sht_plan_destroy(self._h), "sht_plan_destroy")
+            self._h = ctypes.c_void_p()
+
+    def close_async(self, stream):
+        """Release in stream order on ``stream`` without synchronising the
+        device; no work on other streams may still use the plan."""
+        if self._h:
+            _check(self._lib.sht_plan_destroy_async(self._h, _stream_handle(stream)), "sht_plan_destroy_async")
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -40,6 +40,9 @@ class FakeExecutor:
     def resident(self):
         return len(self.tables) * self.table_bytes + self.buf
 
+    def inflight(self):
+        return self.buf
+
     def evictable(self):
         return sum(self.table_bytes for k in self.tables if self.busy.get(k, 0) == 0)
 
@@ -122,6 +125,33 @@ def test_eviction_only_of_idle_tables():
     sched.run(reqs)
     assert ex.evicted, "a 700-byte budget cannot hold every table set"
     assert sched.peak <= 700
+
+
+@pytest.mark.parametrize("bypass", [1, 4])
+def test_bounded_bypass_of_a_waiting_head(bypass):
+    # mixed sizes under a tight budget: requests may pass a head that waits
+    # for memory, at most `bypass` per waiting head; all complete in budget
+    clock = MockClock()
+    ex = FakeExecutor(clock, table_bytes=50)
+    rng = random.Random(11)
+    reqs, t = [], 0.0
+    for i in range(200):
+        t += rng.expovariate(400.0)
+        reqs.append(Request(i, t, rng.choice([1, 2, 3]), rng.choice([1, 2, 40]), "fp32"))
+    sched = Scheduler(ex, 4, 700, clock=clock, idle=clock.advance, bypass=bypass)
+    done = sched.run(reqs)
+    assert len(done) == len(reqs)
+    assert sched.peak <= 700
+    idx = {rid: k for k, rid in enumerate(ex.launched)}  # launch order
+    passed_any = False
+    for r in reqs:
+        # r is the head of the queue once every earlier request has started;
+        # count the later requests that started between then and r's start
+        head_from = max([idx[q.rid] for q in reqs if q.rid < r.rid], default=-1)
+        ahead = [q for q in reqs if q.rid > r.rid and head_from < idx[q.rid] < idx[r.rid]]
+        assert len(ahead) <= bypass, (r.rid, len(ahead))
+        passed_any |= any(idx[q.rid] < idx[r.rid] for q in reqs if q.rid > r.rid)
+    assert passed_any, "no request started ahead of an earlier one"
 
 
 def test_oversized_request_is_refused():
