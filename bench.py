@@ -268,7 +268,9 @@ def run_batch(steps, warmup, precision="fp32"):
     with torch.cuda.stream(stream):
         b = sht.Batch(plans, persistent=True, graph=True)
         ws = b.bind(specs, grids)
+        t_tune = time.time()
         b.tune()
+        out["tune_s"] = time.time() - t_tune
         out["tiles"] = {t: b.tiles().count(t) for t in ("c128", "c64", "c32")}
         for _ in range(warmup):
             b.inverse()

@@ -399,6 +399,12 @@ int sht_batch_tune(sht_batch_t batch, void* hip_stream);
 /* The tile variant chosen for each plan of the batch (n entries). */
 int sht_batch_tiles(sht_batch_t batch, int32_t* out);
 
+/* Set each plan's tile variant (n entries of enum sht_tile, e.g. choices
+ * sht_batch_tune made in an earlier run and kept by the caller) and rebuild
+ * the work lists; drops a captured graph.  SHT_EINVAL if a variant is not
+ * available for the batch's precision.  Synchronises `hip_stream`. */
+int sht_batch_set_tiles(sht_batch_t batch, const int32_t* tiles, void* hip_stream);
+
 int sht_batch_destroy(sht_batch_t batch);
 
 /* Human-readable text of a status code. */

@@ -1467,6 +1467,14 @@ int sht_batch_tune(sht_batch_t b, void* stream) {
   return batch_upload(b, s);
 }
 
+int sht_batch_set_tiles(sht_batch_t b, const int32_t* tiles, void* stream) {
+  if (!b || !tiles) return SHT_EINVAL;
+  for (int i = 0; i < b->n; ++i)
+    if (!legendre_variant_supported(b->prec, tiles[i])) return SHT_EINVAL;
+  for (int i = 0; i < b->n; ++i) b->variant[i] = tiles[i];
+  return batch_upload(b, (hipStream_t)stream);
+}
+
 int sht_batch_tiles(sht_batch_t b, int32_t* out) {
   if (!b || !out) return SHT_EINVAL;
   for (int i = 0; i < b->n; ++i) out[i] = b->variant[i];

@@ -1193,7 +1193,8 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const De
 bool legendre_variant_supported(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C64 || variant == TILE_C32;
   if (prec == SHT_FP32) return variant >= 0 && variant < NUM_TILE_VARIANTS;
-  // bf16x3: synthesis 128 x 64 (C64) or 256 x 128 (C128); analysis 64 k x 128 columns
+  // bf16x3: synthesis 128 x 64 (C64) or 256 x 128 (C128); analysis 64 k x 128
+  // columns in both
   return variant == TILE_C64 || variant == TILE_C128;
 }
 
@@ -1219,6 +1220,7 @@ static const void* inverse_fn(int prec, int variant) {
 }
 
 static int inverse_threads(int prec, int variant) { return (prec == SHT_BF16X3 && variant == TILE_C128) ? 512 : 256; }
+static int direct_threads(int, int) { return 256; }
 
 static const void* direct_fn(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C32 ? fn(DIR_F64_C32) : fn(DIR_F64_C64);
@@ -1230,7 +1232,7 @@ static const void* direct_fn(int prec, int variant) {
 int legendre_blocks_per_cu(int prec, int variant, bool inverse) {
   int n = 0;
   const void* f = inverse ? inverse_fn(prec, variant) : direct_fn(prec, variant);
-  const int threads = inverse ? inverse_threads(prec, variant) : 256;
+  const int threads = inverse ? inverse_threads(prec, variant) : direct_threads(prec, variant);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, threads, 0) != hipSuccess || n < 1) n = 1;
   return n;
 }
@@ -1253,7 +1255,8 @@ hipError_t launch_legendre_direct(const DevPlan* plans, int prec, int variant, c
                                   const IoBind* io, IoBind io0, int grid_blocks, hipStream_t s) {
   if (nitems == 0) return hipSuccess;
   if (!legendre_variant_supported(prec, variant)) return hipErrorInvalidValue;
-  return launch(direct_fn(prec, variant), 256, grid_blocks, s, plans, items, nitems, io, io0);
+  return launch(direct_fn(prec, variant), direct_threads(prec, variant), grid_blocks, s, plans, items, nitems, io,
+                io0);
 }
 
 }  // namespace shtmi

@@ -78,6 +78,7 @@ _SIGNATURES = {
     "sht_batch_direct": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sht_batch_tune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "sht_batch_tiles": (ctypes.c_int, [ctypes.c_void_p, _c_int_p]),
+    "sht_batch_set_tiles": (ctypes.c_int, [ctypes.c_void_p, _c_int_p, ctypes.c_void_p]),
     "sht_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sht_plan_create_vector": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
@@ -488,8 +489,42 @@ class Batch:
     def direct(self, stream=None):
         _check(self._lib.sht_batch_direct(self._h, _stream_handle(stream)), "sht_batch_direct")
 
-    def tune(self, stream=None):
+    def tune(self, stream=None, cache=None):
+        """Pick each plan's tile variant by timing (sht_batch_tune).  With
+        ``cache`` (a JSON file path), choices made before on this device for
+        the same (truncation, grid, fields, precision) are applied without
+        timing, and new ones are added to the file."""
+        import json
+
+        if cache is None:
+            _check(self._lib.sht_batch_tune(self._h, _stream_handle(stream)), "sht_batch_tune")
+            return self.tiles()
+        import torch
+
+        dev = torch.cuda.get_device_properties(torch.cuda.current_device())
+        arch = getattr(dev, "gcnArchName", dev.name)
+        keys = [f"{arch}|T{p.truncation}|{p.grid}|F{p.nfields}|{p.precision}" for p in self.plans]
+        try:
+            with open(cache) as fh:
+                known = json.load(fh)
+        except (OSError, ValueError):
+            known = {}
+        if all(k in known for k in keys):
+            tiles = (ctypes.c_int32 * len(self.plans))(*[TILES[known[k]] for k in keys])
+            _check(self._lib.sht_batch_set_tiles(self._h, tiles, _stream_handle(stream)), "sht_batch_set_tiles")
+            return self.tiles()
         _check(self._lib.sht_batch_tune(self._h, _stream_handle(stream)), "sht_batch_tune")
+        chosen = self.tiles()
+        known.update(dict(zip(keys, chosen)))
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(known, fh, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+        return chosen
+
+    def set_tiles(self, tiles, stream=None):
+        arr = (ctypes.c_int32 * len(self.plans))(*[TILES[t] for t in tiles])
+        _check(self._lib.sht_batch_set_tiles(self._h, arr, _stream_handle(stream)), "sht_batch_set_tiles")
 
     def tiles(self):
         out = (ctypes.c_int32 * len(self.plans))()

@@ -142,6 +142,32 @@ def test_tuned_batch_equals_alone(sht):
         p.close()
 
 
+def test_tuning_cache_round_trip(sht, tmp_path):
+    plans, specs, _ = _make(sht, "fp32")
+    grids = [p.empty_grid() for p in plans]
+    cache = str(tmp_path / "tiles.json")
+    b = sht.Batch(plans, persistent=True)
+    b.bind(specs, grids)
+    first = b.tune(cache=cache)
+    b.inverse()
+    torch.cuda.synchronize()
+    ref = [g.clone() for g in grids]
+    b.close()
+    # a new batch over the same shapes takes the stored choices without timing
+    b2 = sht.Batch(plans, persistent=True)
+    b2.bind(specs, grids)
+    b2.set_tiles(["c32"] * len(plans))
+    assert b2.tiles() == ["c32"] * len(plans)
+    assert b2.tune(cache=cache) == first
+    b2.inverse()
+    torch.cuda.synchronize()
+    for g, r in zip(grids, ref):
+        assert torch.equal(g, r)
+    b2.close()
+    for p in plans:
+        p.close()
+
+
 @pytest.mark.parametrize("tile", ["c128", "c64", "c32"])
 def test_tile_variants_agree(sht, tile):
     with sht.Plan(63, "octahedral", 21, "fp32") as plan:
