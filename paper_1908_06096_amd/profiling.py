@@ -3,9 +3,14 @@
     python -m paper_1908_06096_amd.profiling stats  <kernel_stats.csv> <out.md> "<command>"
     python -m paper_1908_06096_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <copy_bytes> <out.json> "<commands>"
+    python -m paper_1908_06096_amd.profiling sq <counter_collection.csv> <out.md> "<command>"
 
 ``stats`` turns a ``--kernel-trace --stats`` summary into a short markdown
-table.  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+table.  ``sq`` summarises an SQ/GRBM counter run per kernel: MFMA pipe busy
+(SQ_VALU_MFMA_BUSY_CYCLES over the active cycles of all 1024 SIMDs; the
+GRBM_GUI_ACTIVE reading is the sum over the 8 XCDs), the MFMA work issued
+(SQ_INSTS_VALU_MFMA_MOPS_* x 512 flops) and VALU issue (SQ_INSTS_VALU, a
+wave64 instruction holding a SIMD for 4 cycles).  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
 runs into HBM bytes per dispatch for each kernel, scaled by what the same
 counters read for a plain device copy of ``copy_bytes`` bytes captured in the
 same runs (the runtime's ``copyBuffer`` dispatch whose write counter is the
@@ -122,6 +127,53 @@ def traffic_json(fetch_csv, write_csv, copy_bytes, out_json, commands):
         fh.write("\n")
 
 
+SIMDS = 1024  # 256 CUs x 4 SIMDs
+XCDS = 8
+
+
+def sq_markdown(csv_path, out_md, command):
+    per = defaultdict(lambda: defaultdict(list))  # kernel -> counter -> per-dispatch values
+    dur = defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        k = _short(r["Kernel_Name"])
+        per[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur[k][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+    lines = [
+        "# SQ counters per kernel (averages per dispatch)",
+        "",
+        "Command:",
+        "",
+        "```",
+        command,
+        "```",
+        "",
+        "MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 1024 SIMDs); MFMA Tflop issued = "
+        "SQ_INSTS_VALU_MFMA_MOPS_{F32,BF16,F64} x 512 (padding included); VALU busy = SQ_INSTS_VALU x 4 / "
+        "(GRBM_GUI_ACTIVE / 8 x 1024).",
+        "",
+        "| kernel | dispatches | ms | MFMA busy | MFMA Tflop issued (F32 / BF16 / F64) | VALU instr | VALU busy |",
+        "|---|---|---|---|---|---|---|",
+    ]
+    for k in sorted(per, key=lambda x: -sum(dur[x].values())):
+        c = per[k]
+        if "shtmi" not in k and "legendre" not in k and "fourier" not in k:
+            continue
+
+        def avg(name):
+            v = c.get(name, [0.0])
+            return sum(v) / len(v)
+
+        active = avg("GRBM_GUI_ACTIVE") / XCDS * SIMDS
+        mfma = avg("SQ_VALU_MFMA_BUSY_CYCLES") / active if active else 0.0
+        valu = avg("SQ_INSTS_VALU") * 4 / active if active else 0.0
+        mops = [avg("SQ_INSTS_VALU_MFMA_MOPS_" + t) * 512 / 1e12 for t in ("F32", "BF16", "F64")]
+        ms = sum(dur[k].values()) / len(dur[k])
+        lines.append("| `%s` | %d | %.3f | %.1f%% | %.3f / %.3f / %.3f | %.3g | %.1f%% |" % (
+            k, len(dur[k]), ms, 100 * mfma, mops[0], mops[1], mops[2], avg("SQ_INSTS_VALU"), 100 * valu))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def measured_traffic(path, stage):
     """HBM bytes per call of ``stage`` (all its kernels) from a committed
     traffic file, or None when the file is absent or the kernel sources
@@ -143,5 +195,7 @@ if __name__ == "__main__":
         stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
     elif sys.argv[1] == "traffic":
         traffic_json(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6])
+    elif sys.argv[1] == "sq":
+        sq_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
         raise SystemExit(__doc__)
