@@ -125,6 +125,9 @@ typedef struct sht_info {
   int64_t own_bytes;     /* device bytes of the plan without the shared tables */
   int32_t vector;        /* 1 for plans of sht_plan_create_vector, else 0 */
   int32_t degree;        /* highest degree of the Pbar tables: N, or N + 1 for vector plans */
+  int32_t table_free;    /* 1 for plans of sht_plan_create_table_free, else 0 */
+  int32_t reserved;
+  int64_t chunk_table_bytes; /* table-free plans: bytes of one chunk's tables (in the workspace) */
 } sht_info;
 
 /* Pointwise spectral operators (sht_spectral_op), on the unit sphere. */
@@ -160,6 +163,23 @@ enum sht_batch_flags {
  * for SHT_GRID_FULL), `nfields` >= 1.  On success *out receives the plan. */
 int sht_plan_create(sht_plan_t* out, int truncation, int grid, int nfields,
                     int precision, void* hip_stream);
+
+/* A plan that keeps no Pbar tables resident, for truncations whose tables
+ * would not fit the device (they grow as N^3: 3.6 GB in FP32 at TCo1279,
+ * ~0.5 TB at T8191): the wavenumbers are cut into chunks whose tables fit
+ * `chunk_bytes` (0: 256 MiB; a wavenumber whose tables alone are larger is
+ * a chunk by itself), and each transform makes a chunk's tables in its workspace
+ * (float64 recurrence, the same kernel and values as the resident tables
+ * of sht_plan_create) right before that chunk's Legendre product.  Results
+ * are bitwise those of a plan from sht_plan_create with the same arguments
+ * (same tables, same product kernels and summation order); each transform
+ * pays for making the tables.  Arguments and errors as sht_plan_create.
+ * Serves sht_inverse, sht_direct, the stage calls (which then need the
+ * whole workspace: sht_workspace_size covers the Fourier buffer and one
+ * chunk's tables), sht_stepper_*; not batches, sht_plan_legendre_table or
+ * sht_transform_static beyond its scratch. */
+int sht_plan_create_table_free(sht_plan_t* out, int truncation, int grid, int nfields, int precision,
+                               size_t chunk_bytes, void* hip_stream);
 
 /* A plan for `nfields` fields that shares every device table of `base`
  * (same truncation, grid and precision): only its descriptor and work lists

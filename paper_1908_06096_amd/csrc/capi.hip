@@ -172,6 +172,9 @@ int default_variant(int prec, int F) {
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Tables of one chunk of wavenumbers in a table-free plan (bytes).
+constexpr int64_t kChunkTableBytes = (int64_t)256 << 20;
+
 }  // namespace
 
 int shtmi::hip_status(hipError_t e) {
@@ -223,6 +226,18 @@ struct sht_plan_s {
   int64_t tab_plane = 0;
   size_t tab_bytes = 0, fft_bytes = 0;
   size_t inv_cap = 0, dir_cap = 0;  // work items the arena holds
+  int64_t ncoef = 0;                 // (a_n, e_n) pairs of the recurrence
+  // table-free plans: no resident Pbar tables; the wavenumbers are cut into
+  // chunks [chunk_m[c], chunk_m[c + 1]) whose tables (at most chunk_bytes,
+  // offsets relative to the chunk) are made in the workspace right before
+  // each chunk's product; inv_off / dir_off index each chunk's work items
+  int notab = 0;
+  int64_t chunk_limit = 0;  // requested bytes per chunk
+  std::vector<int> chunk_m;
+  std::vector<int> inv_off, dir_off;
+  size_t chunk_bytes = 0;
+  double* d_sect = nullptr;
+  double2* d_coef = nullptr;
   size_t lds_syn = 0, lds_ana = 0;            // largest of the tiers'
   size_t lds_syn_t[FFT_TIERS] = {}, lds_ana_t[FFT_TIERS] = {};
   int max_Lp = 0;
@@ -301,12 +316,37 @@ void legendre_arrange(std::vector<WorkItem>* items, Steps steps) {
 }
 
 // Arranged work lists of one plan.
+// Arranged work lists of one plan.  For a table-free plan the lists are the
+// chunks' lists back to back; inv_off / dir_off (if given) receive where
+// each chunk's items start (nchunks + 1 entries).
 void legendre_items(const sht_plan_s* p, int variant, int plan, std::vector<WorkItem>* inv,
-                    std::vector<WorkItem>* dir) {
-  legendre_items_raw(p, variant, plan, inv, dir);
-  // synthesis tiles step through k, analysis tiles through the rings
-  legendre_arrange(inv, [&](const WorkItem& w) { return (double)std::max(p->ms[w.m].Kp[0], p->ms[w.m].Kp[1]) + 8.0; });
-  legendre_arrange(dir, [&](const WorkItem& w) { return (double)p->ms[w.m].Lp + 8.0; });
+                    std::vector<WorkItem>* dir, std::vector<int>* inv_off = nullptr,
+                    std::vector<int>* dir_off = nullptr) {
+  auto steps_inv = [&](const WorkItem& w) { return (double)std::max(p->ms[w.m].Kp[0], p->ms[w.m].Kp[1]) + 8.0; };
+  auto steps_dir = [&](const WorkItem& w) { return (double)p->ms[w.m].Lp + 8.0; };
+  if (!p->notab) {
+    legendre_items_raw(p, variant, plan, inv, dir);
+    // synthesis tiles step through k, analysis tiles through the rings
+    legendre_arrange(inv, steps_inv);
+    legendre_arrange(dir, steps_dir);
+    return;
+  }
+  if (inv_off) inv_off->assign(1, 0);
+  if (dir_off) dir_off->assign(1, 0);
+  for (size_t c = 0; c + 1 < p->chunk_m.size(); ++c) {
+    sht_plan_s part;  // the chunk's wavenumbers
+    part.prec = p->prec;
+    part.F = p->F;
+    part.ms.assign(p->ms.begin() + p->chunk_m[c], p->ms.begin() + p->chunk_m[c + 1]);
+    std::vector<WorkItem> a, b;
+    legendre_items_raw(&part, variant, plan, &a, &b);
+    legendre_arrange(&a, steps_inv);
+    legendre_arrange(&b, steps_dir);
+    inv->insert(inv->end(), a.begin(), a.end());
+    dir->insert(dir->end(), b.begin(), b.end());
+    if (inv_off) inv_off->push_back((int)inv->size());
+    if (dir_off) dir_off->push_back((int)dir->size());
+  }
 }
 
 // FFT work items (chunks of up to FFT_FCHUNK fields) of one plan, longest
@@ -551,12 +591,35 @@ int build_host(sht_plan_s* p) {
     mi.toff[1] = toff + (int64_t)mi.Kp[0] * mi.Lp;
     toff = mi.toff[1] + (int64_t)mi.Kp[1] * mi.Lp;
     mi.spec_off = (int64_t)m * (2 * D + 3 - m) / 2;
+    mi.coff = p->ncoef;
+    p->ncoef += pbar_coef_count(D, m);
     p->max_Lp = std::max(p->max_Lp, mi.Lp);
     p->ms.push_back(mi);
   }
   p->tab_plane = toff;
   const int tab_elem = (p->prec == SHT_FP64) ? 8 : 4;  // BF16 split: two 2-byte planes
   p->tab_bytes = (size_t)toff * tab_elem;
+  if (p->notab) {
+    // chunks of consecutive wavenumbers whose tables fit kChunkTableBytes
+    // (or one wavenumber, if a single one is larger), offsets per chunk
+    p->chunk_m.assign(1, 0);
+    int64_t used = 0, most = 0;
+    for (MInfo& mi : p->ms) {
+      const int64_t need = ((int64_t)mi.Kp[0] + mi.Kp[1]) * mi.Lp;
+      if (used > 0 && (used + need) * tab_elem > p->chunk_limit) {
+        p->chunk_m.push_back(mi.m);
+        used = 0;
+      }
+      mi.toff[0] = used;
+      mi.toff[1] = used + (int64_t)mi.Kp[0] * mi.Lp;
+      used += need;
+      most = std::max(most, used);
+    }
+    p->chunk_m.push_back(N + 1);
+    p->tab_plane = most;  // the BF16 lo plane starts here in the chunk scratch
+    p->chunk_bytes = (size_t)most * tab_elem;
+    p->tab_bytes = 0;
+  }
   if (p->vec) {
     // H table: degrees m..N; plane 0 odd n - m, plane 1 even n - m.  Its
     // products write degree n at spec_off + parity + 2k of the wind layout
@@ -579,7 +642,7 @@ int build_host(sht_plan_s* p) {
 
   // ---- work lists (m ascending = cost descending for both products) ----
   p->variant = default_variant(p->prec, p->F);
-  legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
+  legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items, &p->inv_off, &p->dir_off);
   {
     std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
     fft_items(p, 0, st, at);
@@ -631,7 +694,7 @@ int build_own(sht_plan_s* p, hipStream_t s) {
 }
 
 int build_device(sht_plan_s* p, hipStream_t s) {
-  void *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft, *v_wa, *v_hms, *v_htab;
+  void *v_rings, *v_cls, *v_ms, *v_mu, *v_w, *v_tab, *v_fft, *v_wa, *v_hms, *v_htab, *v_sect, *v_coef;
   struct Part {
     void** dst;
     size_t bytes;
@@ -647,6 +710,8 @@ int build_device(sht_plan_s* p, hipStream_t s) {
       {&v_wa, p->vec ? sizeof(double) * p->nlat : 0},
       {&v_hms, sizeof(MInfo) * p->hms.size()},
       {&v_htab, p->htab_bytes},
+      {&v_sect, sizeof(double) * (p->ndeg + 1)},
+      {&v_coef, sizeof(double2) * p->ncoef},
   };
   size_t total = 0;
   for (const Part& q : parts) total += align256(q.bytes);
@@ -698,8 +763,13 @@ int build_device(sht_plan_s* p, hipStream_t s) {
 
   HIP_TRY(launch_gauss(p->nlat, (double*)v_mu, (double*)v_w, s));
   if (p->vec) HIP_TRY(launch_analysis_weight(p->nlat, (const double*)v_mu, (const double*)v_w, (double*)v_wa, s));
-  HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane,
-                             p->vec ? p->d_hms : nullptr, v_htab, p->htab_plane, p->N, s));
+  p->d_sect = (double*)v_sect;
+  p->d_coef = (double2*)v_coef;
+  HIP_TRY(launch_pbar_coef(p->ndeg, p->d_ms, (int)p->ms.size(), (double*)v_sect, (double2*)v_coef, s));
+  if (!p->notab)
+    HIP_TRY(launch_pbar_planes(d, p->prec, p->d_ms, (int)p->ms.size(), p->max_Lp, v_tab, p->tab_plane,
+                               p->vec ? p->d_hms : nullptr, v_htab, p->htab_plane, p->N, (const double*)v_sect,
+                               (const double2*)v_coef, s));
   HIP_TRY(launch_fft_tables(d, p->prec, p->d_cls, (int)p->classes.size(), p->classes.data(), v_fft, s));
   HIP_TRY(ensure_lds(std::max(p->lds_syn, p->lds_ana)));
   HIP_TRY(hipStreamSynchronize(s));
@@ -945,9 +1015,11 @@ void release_own(sht_plan_s* p) {
   p->arena = nullptr;
 }
 
-int plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int precision, bool vec, void* hip_stream) {
+int plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int precision, bool vec, void* hip_stream,
+                bool notab = false, int64_t chunk_limit = 0) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
+  if (vec && notab) return SHT_EUNSUPPORTED;
   if (truncation < 1 || nfields < 1 || nfields > (vec ? (1 << 29) : (1 << 30))) return SHT_EINVAL;
   if (grid != SHT_GRID_FULL && grid != SHT_GRID_OCTAHEDRAL) return SHT_EINVAL;
   if (precision != SHT_FP64 && precision != SHT_FP32 && precision != SHT_BF16X3) return SHT_EINVAL;
@@ -956,6 +1028,8 @@ int plan_create(sht_plan_t* out, int truncation, int grid, int nfields, int prec
   p->N = truncation;
   p->grid = grid;
   p->vec = vec ? 1 : 0;
+  p->notab = notab ? 1 : 0;
+  p->chunk_limit = chunk_limit > 0 ? chunk_limit : kChunkTableBytes;
   p->ndeg = truncation + (vec ? 1 : 0);
   p->Fv = nfields;
   p->F = vec ? 2 * nfields : nfields;
@@ -984,6 +1058,12 @@ int sht_plan_create_vector(sht_plan_t* out, int truncation, int grid, int nfield
   return plan_create(out, truncation, grid, nfields, precision, true, hip_stream);
 }
 
+int sht_plan_create_table_free(sht_plan_t* out, int truncation, int grid, int nfields, int precision,
+                               size_t chunk_bytes, void* hip_stream) {
+  if (chunk_bytes > ((size_t)1 << 40)) return SHT_EINVAL;
+  return plan_create(out, truncation, grid, nfields, precision, false, hip_stream, true, (int64_t)chunk_bytes);
+}
+
 int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hip_stream) {
   if (!out) return SHT_EINVAL;
   *out = nullptr;
@@ -997,6 +1077,12 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->ndeg = base->ndeg;
   p->nspec_d = base->nspec_d;
   p->hms = base->hms;
+  p->notab = base->notab;
+  p->chunk_limit = base->chunk_limit;
+  p->chunk_m = base->chunk_m;
+  p->chunk_bytes = base->chunk_bytes;
+  p->d_sect = base->d_sect;
+  p->d_coef = base->d_coef;
   p->htab_plane = base->htab_plane;
   p->htab_bytes = base->htab_bytes;
   p->d_hms = base->d_hms;
@@ -1034,7 +1120,7 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->dph.F = p->F;
   p->dph.Fp = p->Fp;
   p->variant = default_variant(p->prec, p->F);
-  legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items);
+  legendre_items(p, p->variant, 0, &p->inv_items, &p->dir_items, &p->inv_off, &p->dir_off);
   {
     std::vector<FftItem> st[FFT_TIERS], at[FFT_TIERS];
     fft_items(p, 0, st, at);
@@ -1105,6 +1191,8 @@ int sht_plan_info(sht_plan_t p, sht_info* out) {
   out->tile = p->variant;
   out->vector = p->vec;
   out->degree = p->ndeg;
+  out->table_free = p->notab;
+  out->chunk_table_bytes = (int64_t)p->chunk_bytes;
   return SHT_OK;
 }
 
@@ -1123,7 +1211,7 @@ int sht_plan_geometry(sht_plan_t p, double* mu, double* w, int32_t* nlon, int32_
 }
 
 int sht_plan_legendre_table(sht_plan_t p, int m, double* out, int32_t* first_ring) {
-  if (!p || m < 0 || m > p->N) return SHT_EINVAL;
+  if (!p || m < 0 || m > p->N || p->notab) return SHT_EINVAL;
   const MInfo& mi = p->ms[m];
   if (first_ring) *first_ring = mi.first_ring;
   if (!out) return SHT_OK;
@@ -1141,7 +1229,8 @@ int sht_plan_legendre_table(sht_plan_t p, int m, double* out, int32_t* first_rin
 int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
   if (!p || !legendre_variant_supported(p->prec, tile)) return SHT_EINVAL;
   std::vector<WorkItem> inv, dir;
-  legendre_items(p, tile, 0, &inv, &dir);
+  std::vector<int> inv_off, dir_off;
+  legendre_items(p, tile, 0, &inv, &dir, &inv_off, &dir_off);
   const hipStream_t s = (hipStream_t)stream;
   HIP_TRY(hipStreamSynchronize(s));
   if (inv.size() > p->inv_cap || dir.size() > p->dir_cap) {
@@ -1166,6 +1255,9 @@ int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
     p->inv_items = inv;
     p->dir_items = dir;
     p->variant = tile;
+    std::vector<int> keep_io = p->inv_off, keep_do = p->dir_off;
+    p->inv_off = inv_off;
+    p->dir_off = dir_off;
     const int rc = build_own(p, s);
     if (rc != SHT_OK) {
       if (p->arena) {
@@ -1177,6 +1269,8 @@ int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
       p->inv_items.swap(keep.inv_items);
       p->dir_items.swap(keep.dir_items);
       p->variant = keep.variant;
+      p->inv_off = keep_io;
+      p->dir_off = keep_do;
       p->inv_cap = keep.inv_cap;
       p->dir_cap = keep.dir_cap;
       p->d_self = keep.d_self;
@@ -1198,6 +1292,8 @@ int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
   HIP_TRY(hipMemcpy(p->d_dir, dir.data(), sizeof(WorkItem) * dir.size(), hipMemcpyHostToDevice));
   p->inv_items = inv;
   p->dir_items = dir;
+  p->inv_off = inv_off;
+  p->dir_off = dir_off;
   p->variant = tile;
   return SHT_OK;
 }
@@ -1205,6 +1301,7 @@ int sht_plan_set_tile(sht_plan_t p, int tile, void* stream) {
 size_t sht_workspace_size(sht_plan_t p) {
   if (!p) return 0;
   const size_t four = (size_t)p->nfour * p->Fp * 2 * p->elem;
+  if (p->notab) return align256(four) + p->chunk_bytes;  // the Fourier buffer, then one chunk's tables
   if (!p->vec) return four;
   // vector plans: the Fourier buffer, then two arrays of wind coefficients
   // of degree N + 1 (synthesis input / Pbar projections, and H projections)
@@ -1217,9 +1314,32 @@ namespace {
 
 // The stages on a plan's internal layouts (degree ndeg, F fields or
 // components); the public stage calls add the checks of the scalar layout.
+// Table-free plans: each chunk of wavenumbers has its tables made in the
+// workspace (after the Fourier buffer), then its product runs on them.
+void* chunk_tables(sht_plan_t p, void* ws) { return (char*)ws + align256((size_t)p->nfour * p->Fp * 2 * p->elem); }
+
+hipError_t make_chunk_tables(sht_plan_t p, int c, void* tab, hipStream_t s) {
+  const int m0 = p->chunk_m[c], nm = p->chunk_m[c + 1] - m0;
+  return launch_pbar_planes(p->dp, p->prec, p->d_ms + m0, nm, p->max_Lp, tab, p->tab_plane, nullptr, nullptr, 0,
+                            p->N, p->d_sect, p->d_coef, s);
+}
+
 int stage_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* stream) {
+  const hipStream_t s = (hipStream_t)stream;
+  if (p->notab) {
+    void* tab = chunk_tables(p, four);
+    IoBind io = bind_of(spec, nullptr, four);
+    io.pad = tab;
+    for (size_t c = 0; c + 1 < p->chunk_m.size(); ++c) {
+      HIP_TRY(make_chunk_tables(p, (int)c, tab, s));
+      const int n = p->inv_off[c + 1] - p->inv_off[c];
+      HIP_TRY(launch_legendre_inverse(p->d_self, p->prec, p->variant, p->d_inv + p->inv_off[c], n, nullptr, io, n,
+                                      s));
+    }
+    return SHT_OK;
+  }
   HIP_TRY(launch_legendre_inverse(p->d_self, p->prec, p->variant, p->d_inv, (int)p->inv_items.size(), nullptr,
-                                  bind_of(spec, nullptr, four), (int)p->inv_items.size(), (hipStream_t)stream));
+                                  bind_of(spec, nullptr, four), (int)p->inv_items.size(), s));
   return SHT_OK;
 }
 
@@ -1236,8 +1356,20 @@ int stage_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* str
 }
 
 int stage_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream) {
+  const hipStream_t s = (hipStream_t)stream;
+  if (p->notab) {
+    void* tab = chunk_tables(p, const_cast<void*>(four));
+    IoBind io = bind_of(spec, nullptr, four);
+    io.pad = tab;
+    for (size_t c = 0; c + 1 < p->chunk_m.size(); ++c) {
+      HIP_TRY(make_chunk_tables(p, (int)c, tab, s));
+      const int n = p->dir_off[c + 1] - p->dir_off[c];
+      HIP_TRY(launch_legendre_direct(p->d_self, p->prec, p->variant, p->d_dir + p->dir_off[c], n, nullptr, io, n, s));
+    }
+    return SHT_OK;
+  }
   HIP_TRY(launch_legendre_direct(p->d_self, p->prec, p->variant, p->d_dir, (int)p->dir_items.size(), nullptr,
-                                 bind_of(spec, nullptr, four), (int)p->dir_items.size(), (hipStream_t)stream));
+                                 bind_of(spec, nullptr, four), (int)p->dir_items.size(), s));
   return SHT_OK;
 }
 
@@ -1335,7 +1467,7 @@ int sht_batch_create(sht_batch_t* out, const sht_plan_t* plans, int n, int flags
   *out = nullptr;
   if (!plans || n < 1 || (flags & ~(SHT_BATCH_PERSISTENT | SHT_BATCH_GRAPH))) return SHT_EINVAL;
   for (int i = 0; i < n; ++i)
-    if (!scalar_plan(plans[i]) || plans[i]->prec != plans[0]->prec) return SHT_EINVAL;
+    if (!scalar_plan(plans[i]) || plans[i]->notab || plans[i]->prec != plans[0]->prec) return SHT_EINVAL;
   sht_batch_s* b = new (std::nothrow) sht_batch_s();
   if (!b) return SHT_ENOMEM;
   b->n = n;

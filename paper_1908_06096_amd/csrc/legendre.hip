@@ -1114,8 +1114,9 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_kernel(const DevPlan*
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
     if (it.m < 0) continue;  // empty slot of the work list
-    const DevPlan p = gload(plans + it.plan);
+    DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
+    if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
     inverse_tile<T, BM, BN, KI, WCOL>(p, it, (const T*)b.spec, (T*)b.ws);
   }
 }
@@ -1127,8 +1128,9 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(const DevPlan* 
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
     if (it.m < 0) continue;  // empty slot of the work list
-    const DevPlan p = gload(plans + it.plan);
+    DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
+    if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
     direct_tile<T, BC, BK, KJ, WKW>(p, it, (const T*)b.ws, (T*)b.spec);
   }
 }
@@ -1139,8 +1141,9 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_bf16x3_kernel(const D
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
     if (it.m < 0) continue;  // empty slot of the work list
-    const DevPlan p = gload(plans + it.plan);
+    DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
+    if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
     inverse_bf16x3_tile(p, it, (const float*)b.spec, (float*)b.ws);
   }
 }
@@ -1152,8 +1155,9 @@ __global__ __launch_bounds__(512, 1) void legendre_inverse_bf16x3_wide_kernel(co
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
     if (it.m < 0) continue;  // empty slot of the work list
-    const DevPlan p = gload(plans + it.plan);
+    DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
+    if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
     inverse_bf16x3_wide_tile(p, it, (const float*)b.spec, (float*)b.ws);
   }
 }
@@ -1165,8 +1169,9 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const De
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
     if (it.m < 0) continue;  // empty slot of the work list
-    const DevPlan p = gload(plans + it.plan);
+    DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
+    if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
     direct_bf16x3_tile<BC, BK>(p, it, (const float*)b.ws, (float*)b.spec);
   }
 }

@@ -157,6 +157,7 @@ struct MInfo {
   int32_t Kp[2];      // padded to KCH
   int64_t toff[2];    // element offset of each parity table
   int64_t spec_off;   // index(m, m) in the spectral layout
+  int64_t coff;       // first (a_n, e_n) of m in the recurrence coefficients
 };
 
 // A Legendre work item: wavenumber, tile along the table rows or columns,
@@ -185,7 +186,7 @@ struct IoBind {
   void* spec;
   void* grid;
   void* ws;
-  void* pad;
+  void* pad;  // Legendre tables to use instead of the plan's (table-free plans), or null
 };
 
 // Column-tile variants of the Legendre products (2F real columns per m):
@@ -222,7 +223,13 @@ hipError_t launch_gauss(int nlat, double* mu, double* w, hipStream_t s);
 // tables of degree <= Nh in the layout d_hms describes).
 hipError_t launch_pbar_planes(const DevPlan& p, int prec, const MInfo* d_ms, int nm, int max_Lp,
                               void* tab, int64_t plane_elems, const MInfo* d_hms, void* htab, int64_t hplane_elems,
-                              int Nh, hipStream_t s);
+                              int Nh, const double* sect, const double2* coef, hipStream_t s);
+// The recurrence's coefficients: sect[k] (k = 0..D) and, per m, coef[coff(m)
+// + n - m] = (a_n, e_n) for n = m..D.
+hipError_t launch_pbar_coef(int D, const MInfo* d_ms, int nm, double* sect, double2* coef, hipStream_t s);
+// Recurrence coefficients per m for table degree D: n - m = 0 .. 16 b, with
+// b the number of 16-degree blocks covering n = m..D.
+__host__ __device__ inline int pbar_coef_count(int D, int m) { return 16 * ((D - m + 16) / 16) + 1; }
 hipError_t launch_fft_tables(const DevPlan& p, int prec, const FftClass* d_cls, int ncls,
                              const FftClass* h_cls, void* fft, hipStream_t s);
 hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& mi, int64_t plane,

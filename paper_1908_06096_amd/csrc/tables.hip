@@ -58,15 +58,24 @@ hipError_t launch_gauss(int nlat, double* mu, double* w, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Pbar_n^m tables.  Thread (m, r) evaluates the column n = m..N at the r-th
-// north ring carrying m:
-//   Pbar_0^0 = 1/sqrt(2),  Pbar_k^k = sqrt((2k+1)/(2k)) sin(theta) Pbar_{k-1}^{k-1},
-//   Pbar_{m+1}^m = sqrt(2m+3) mu Pbar_m^m,
-//   Pbar_n^m = a (mu Pbar_{n-1}^m - b Pbar_{n-2}^m),
-//   a = sqrt((4n^2-1)/(n^2-m^2)),  b = sqrt(((n-1)^2-m^2)/(4(n-1)^2-1)).
+// Pbar_n^m tables.  Thread (m, r) evaluates the column n = m..D (D the
+// table degree) at the r-th north ring carrying m:
+//   Pbar_0^0 = 1/sqrt(2),  Pbar_k^k = f_k sin(theta) Pbar_{k-1}^{k-1},  f_k = sqrt((2k+1)/(2k)),
+//   Pbar_n^m = a_n (mu Pbar_{n-1}^m - b_n Pbar_{n-2}^m)   (n > m, Pbar_{m-1}^m = 0),
+//   a_n = sqrt((4n^2-1)/(n^2-m^2)),  b_n = e_{n-1},  e_n = sqrt((n^2-m^2)/(4n^2-1)),  e_m = 0
+// (at n = m + 1, a_n = sqrt(2m+3)).  The factors f_k and the pairs
+// (a_n, e_n) per (m, n) are computed once, in float64, by pbar_coef_kernel;
+// in pbar_kernel they are the same for every lane (scalar loads), so no
+// thread takes a square root per n.
 // Even and odd n - m go to separate tables (parity 0 and 1); within a table
 // element (row r, k) with n = m + parity + 2k sits in chunk k / KCH at
-// [r][k % KCH].  Padding rows and columns are written as zeros.
+// [r][k % KCH].  The thread walks n - m in blocks of 2 KCH = 16: a block
+// fills exactly one chunk row of each parity (even and odd n - m), so the
+// values stay in registers (static indices) and leave as two 8-value
+// stores; lanes of consecutive rings write consecutive chunk rows.  Past
+// n = D the coefficients are zero, so the recurrence yields zeros there,
+// and rows past L start from zero: padding rows and columns are written as
+// zeros by the same code.
 // ---------------------------------------------------------------------------
 
 __device__ inline uint16_t bf16_rne(float x) {
@@ -81,17 +90,29 @@ struct TabStore {
   int prec;
   void* tab;
   int64_t total;  // elements per plane (bf16 split: hi plane then lo plane)
-  __device__ void put(int64_t e, double v) const {
+  // KCH consecutive elements from e (a multiple of KCH), rounded once each
+  __device__ void put8(int64_t e, const double* v) const {
+    static_assert(KCH == 8, "chunk rows of 8");
     if (prec == SHT_FP64) {
-      ((double*)tab)[e] = v;
+      double2* d = (double2*)((double*)tab + e);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gstore(d + i, make_double2(v[2 * i], v[2 * i + 1]));
     } else if (prec == SHT_FP32) {
-      ((float*)tab)[e] = (float)v;
+      float4* d = (float4*)((float*)tab + e);
+      gstore(d, make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]));
+      gstore(d + 1, make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]));
     } else {
-      const float x = (float)v;
-      const uint16_t hi = bf16_rne(x);
-      const uint16_t lo = bf16_rne(x - bf16_to_float(hi));
-      ((uint16_t*)tab)[e] = hi;
-      ((uint16_t*)tab)[total + e] = lo;
+      uint32_t h[4], l[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float x0 = (float)v[2 * i], x1 = (float)v[2 * i + 1];
+        const uint16_t h0 = bf16_rne(x0), h1 = bf16_rne(x1);
+        const uint16_t l0 = bf16_rne(x0 - bf16_to_float(h0)), l1 = bf16_rne(x1 - bf16_to_float(h1));
+        h[i] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+        l[i] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      }
+      gstore((uint4*)((uint16_t*)tab + e), make_uint4(h[0], h[1], h[2], h[3]));
+      gstore((uint4*)((uint16_t*)tab + total + e), make_uint4(l[0], l[1], l[2], l[3]));
     }
   }
 };
@@ -100,78 +121,112 @@ __device__ inline int64_t tab_index(const MInfo& mi, int par, int r, int k) {
   return mi.toff[par] + (int64_t)(k / KCH) * mi.Lp * KCH + (int64_t)r * KCH + (k % KCH);
 }
 
+// Coefficients: f_k (k = 0..D; f_0 unused) and, per m, (a_n, e_n) at
+// coef[coff(m) + n - m] for n - m = 0..pbar_coef_count(D, m) - 1, zero
+// where n - m = 0 (a_m and e_m) or n > D.
+__global__ void pbar_coef_kernel(int D, const MInfo* ms, int nm, double* sect, double2* coef) {
+  const int m = blockIdx.y;
+  if (m >= nm) return;
+  const MInfo mi = ms[m];
+  const int cnt = pbar_coef_count(D, mi.m);
+  for (int d = blockIdx.x * blockDim.x + threadIdx.x; d < cnt; d += gridDim.x * blockDim.x) {
+    const int n = mi.m + d;
+    const double nn = (double)n * n, mm = (double)mi.m * mi.m;
+    const bool live = d >= 1 && n <= D;
+    const double a = live ? sqrt((4.0 * nn - 1.0) / (nn - mm)) : 0.0;
+    const double e = live ? sqrt((nn - mm) / (4.0 * nn - 1.0)) : 0.0;
+    coef[mi.coff + d] = make_double2(a, e);
+  }
+  if (m == 0)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= D; k += gridDim.x * blockDim.x)
+      sect[k] = k >= 1 ? sqrt((2.0 * k + 1.0) / (2.0 * k)) : 0.0;
+}
+
 // Vector plans also store H_k^m = (1 - mu^2) dPbar_k^m/dmu for k = m..Nh
 // (Nh = N, one below the Pbar degree), from the derivative identity
-//   H_k = (k + 1) e_k Pbar_{k-1} - k e_{k+1} Pbar_{k+1},
-//   e_k = sqrt((k^2 - m^2) / (4 k^2 - 1))   (e_m = 0),
-// evaluated as soon as the recurrence has produced Pbar_{k+1}.  H has the
+//   H_k = (k + 1) e_k Pbar_{k-1} - k e_{k+1} Pbar_{k+1}   (e_m = 0),
+// formed in the same blocks of 16 from the Pbar values around k.  H has the
 // opposite parity in mu to Pbar (H_k(-mu) = -(-1)^{k-m} H_k(mu)), so its
 // table puts odd k - m in plane 0 (paired, like Pbar's plane 0, with the
 // symmetric part of the data) and even k - m in plane 1; `hms` describes
 // that layout (K[0] = number of odd k - m, K[1] = number of even).
-__device__ inline double eps_nm(int k, int m) {
-  if (k <= m) return 0.0;
-  return sqrt(((double)k * k - (double)m * m) / (4.0 * (double)k * k - 1.0));
-}
-
-__global__ void pbar_kernel(DevPlan p, const MInfo* ms, TabStore st, const MInfo* hms, TabStore hst, int Nh) {
+__global__ void pbar_kernel(DevPlan p, const MInfo* ms, TabStore st, const MInfo* hms, TabStore hst, int Nh,
+                            const double* sect, const double2* coef) {
+  constexpr int B = 2 * KCH;
   const MInfo mi = ms[blockIdx.y];
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= mi.Lp) return;
   const int m = mi.m;
-  const int N = p.N;
+  const int D = p.N;
   const bool with_h = (hms != nullptr);
   MInfo hi{};
   if (with_h) hi = hms[blockIdx.y];
-  if (r >= mi.L) {
-    for (int par = 0; par < 2; ++par)
-      for (int k = 0; k < mi.Kp[par]; ++k) st.put(tab_index(mi, par, r, k), 0.0);
-    if (with_h)
-      for (int par = 0; par < 2; ++par)
-        for (int k = 0; k < hi.Kp[par]; ++k) hst.put(tab_index(hi, par, r, k), 0.0);
-    return;
+  double x = 0.0, pmm = 0.0;  // rows past L: every value is zero
+  if (r < mi.L) {
+    x = p.mu[mi.first_ring + r];
+    const double s = sqrt((1.0 - x) * (1.0 + x));
+    pmm = 1.0 / sqrt(2.0);
+    for (int k = 1; k <= m; ++k) pmm = sect[k] * s * pmm;
   }
-  const double x = p.mu[mi.first_ring + r];
-  const double s = sqrt((1.0 - x) * (1.0 + x));
-  // H_k once Pbar_{k-1} (pkm1) and Pbar_{k+1} (pkp1) are known
-  auto put_h = [&](int k, double pkm1, double pkp1) {
-    if (!with_h || k > Nh) return;
-    const double h = (k + 1.0) * eps_nm(k, m) * pkm1 - (double)k * eps_nm(k + 1, m) * pkp1;
-    const int d = k - m;
-    hst.put(tab_index(hi, (d & 1) ? 0 : 1, r, d >> 1), h);
-  };
-  double pmm = 1.0 / sqrt(2.0);
-  for (int k = 1; k <= m; ++k) pmm = sqrt((2.0 * k + 1.0) / (2.0 * k)) * s * pmm;
-  st.put(tab_index(mi, 0, r, 0), pmm);
-  if (N > m) {
-    double p2 = pmm;
-    double p1 = sqrt(2.0 * m + 3.0) * x * pmm;
-    st.put(tab_index(mi, 1, r, 0), p1);
-    put_h(m, 0.0, p1);
-    for (int n = m + 2; n <= N; ++n) {
-      const double a = sqrt((4.0 * n * n - 1.0) / ((double)n * n - (double)m * m));
-      const double b = sqrt(((n - 1.0) * (n - 1.0) - (double)m * m) / (4.0 * (n - 1.0) * (n - 1.0) - 1.0));
-      const double pn = a * (x * p1 - b * p2);
-      st.put(tab_index(mi, (n - m) & 1, r, (n - m) >> 1), pn);
-      put_h(n - 1, p2, pn);
+  const double2* cf = coef + mi.coff;
+  const int nb = (D - m + B) / B;  // blocks covering n - m = 0..D - m
+  double prev = 0.0, cur = pmm;   // Pbar at n - m = B c - 1 and B c
+  for (int c = 0; c < nb; ++c) {
+    const double2* q = cf + B * c;
+    double v[B + 1];  // Pbar at n - m = B c + j
+    v[0] = cur;
+    double p2 = prev, p1 = cur;
+#pragma unroll
+    for (int j = 1; j <= B; ++j) {
+      const double pn = q[j].x * __fma_rn(x, p1, -(q[j - 1].y * p2));
+      v[j] = pn;
       p2 = p1;
       p1 = pn;
     }
+    double ev[KCH], od[KCH];
+#pragma unroll
+    for (int i = 0; i < KCH; ++i) {
+      ev[i] = v[2 * i];
+      od[i] = v[2 * i + 1];
+    }
+    st.put8(tab_index(mi, 0, r, KCH * c), ev);
+    if (KCH * c < mi.Kp[1]) st.put8(tab_index(mi, 1, r, KCH * c), od);
+    if (with_h) {
+      double hv[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        const int d = B * c + j, k = m + d;
+        const double below = j == 0 ? prev : v[j - 1];
+        const double h = (k + 1.0) * q[j].y * below - (double)k * q[j + 1].y * v[j + 1];
+        hv[j] = k <= Nh ? h : 0.0;
+      }
+      double hodd[KCH], hev[KCH];
+#pragma unroll
+      for (int i = 0; i < KCH; ++i) {
+        hev[i] = hv[2 * i];
+        hodd[i] = hv[2 * i + 1];
+      }
+      if (KCH * c < hi.Kp[0]) hst.put8(tab_index(hi, 0, r, KCH * c), hodd);
+      if (KCH * c < hi.Kp[1]) hst.put8(tab_index(hi, 1, r, KCH * c), hev);
+    }
+    prev = v[B - 1];
+    cur = v[B];
   }
-  for (int par = 0; par < 2; ++par)
-    for (int k = mi.K[par]; k < mi.Kp[par]; ++k) st.put(tab_index(mi, par, r, k), 0.0);
-  if (with_h)
-    for (int par = 0; par < 2; ++par)
-      for (int k = hi.K[par]; k < hi.Kp[par]; ++k) hst.put(tab_index(hi, par, r, k), 0.0);
 }
 
 hipError_t launch_pbar_planes(const DevPlan& p, int prec, const MInfo* d_ms, int nm, int max_Lp,
                               void* tab, int64_t plane_elems, const MInfo* d_hms, void* htab, int64_t hplane_elems,
-                              int Nh, hipStream_t s) {
+                              int Nh, const double* sect, const double2* coef, hipStream_t s) {
   TabStore st{prec, tab, plane_elems};
   TabStore hst{prec, htab, hplane_elems};
   const int bs = 64;
-  hipLaunchKernelGGL(pbar_kernel, dim3((max_Lp + bs - 1) / bs, nm), dim3(bs), 0, s, p, d_ms, st, d_hms, hst, Nh);
+  hipLaunchKernelGGL(pbar_kernel, dim3((max_Lp + bs - 1) / bs, nm), dim3(bs), 0, s, p, d_ms, st, d_hms, hst, Nh,
+                     sect, coef);
+  return hipGetLastError();
+}
+
+hipError_t launch_pbar_coef(int D, const MInfo* d_ms, int nm, double* sect, double2* coef, hipStream_t s) {
+  hipLaunchKernelGGL(pbar_coef_kernel, dim3(4, nm), dim3(256), 0, s, D, d_ms, nm, sect, coef);
   return hipGetLastError();
 }
 

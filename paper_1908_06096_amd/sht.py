@@ -47,6 +47,9 @@ class SHTInfo(ctypes.Structure):
         ("own_bytes", ctypes.c_int64),
         ("vector", ctypes.c_int32),
         ("degree", ctypes.c_int32),
+        ("table_free", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("chunk_table_bytes", ctypes.c_int64),
     ]
 
 
@@ -82,6 +85,8 @@ _SIGNATURES = {
     "sht_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sht_plan_create_vector": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
                                               ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "sht_plan_create_table_free": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int,
+                                                  ctypes.c_int, ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p]),
     "sht_vector_inverse": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "sht_vector_direct": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
     "sht_gradient": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 4),
@@ -150,7 +155,8 @@ class Plan:
     plan serves F vector fields (vorticity / divergence <-> winds, gradients)
     instead of scalar transforms."""
 
-    def __init__(self, truncation, grid="full", nfields=1, precision="fp64", stream=None, like=None, vector=False):
+    def __init__(self, truncation, grid="full", nfields=1, precision="fp64", stream=None, like=None, vector=False,
+                 table_free=False, chunk_bytes=0):
         lib = library()
         self._lib = lib
         self._h = ctypes.c_void_p()
@@ -160,10 +166,15 @@ class Plan:
             _check(lib.sht_plan_create_like(ctypes.byref(self._h), like._h, int(nfields), _stream_handle(stream)),
                    "sht_plan_create_like")
         else:
-            create = lib.sht_plan_create_vector if vector else lib.sht_plan_create
-            _check(create(ctypes.byref(self._h), int(truncation), GRIDS[grid], int(nfields), PRECISIONS[precision],
-                          _stream_handle(stream)), "sht_plan_create_vector" if vector else "sht_plan_create")
+            args = [ctypes.byref(self._h), int(truncation), GRIDS[grid], int(nfields), PRECISIONS[precision]]
+            if table_free:
+                name = "sht_plan_create_table_free"
+                args.append(ctypes.c_size_t(int(chunk_bytes)))
+            else:
+                name = "sht_plan_create_vector" if vector else "sht_plan_create"
+            _check(getattr(lib, name)(*args, _stream_handle(stream)), name)
         self.vector = bool(vector)
+        self.table_free = bool(table_free) if like is None else like.table_free
         info = SHTInfo()
         _check(lib.sht_plan_info(self._h, ctypes.byref(info)), "sht_plan_info")
         self.info = info
