@@ -1102,6 +1102,229 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
   }
 }
 
+// Analysis in BF16 split precision on a tile of 128 k x 128 real columns,
+// both parities, eight waves, MFMA 32x32x16: out^T[c][k] = sum_j X^T[c][j]
+// T[j][k] over the rings j, 32 rings per step.  Both operands stay in LDS in
+// the order they have in memory -- the table as its chunks ([ring][8 k]),
+// the Fourier data as ring rows of columns -- and are read into the MFMA
+// operand form (8 consecutive rings per lane) with the transposing LDS
+// reads of gfx950 (ds_read_b64_tr_b16: within each group of 16 lanes, lane
+// i receives element i % 4 of the 8-byte reads addressed by lanes
+// 4 t + i / 4, t = 0..3, which was checked on the device).  So the table
+// stage is a straight buffer-to-LDS copy, and the Fourier stage is written
+// row-contiguous after the S/A fold and the split.
+//
+// Wave w computes parity w >> 2 on k half (w >> 1) & 1 and column half
+// w & 1: 2 x 2 blocks of 32 x 32.  Waves whose k half lies past K skip
+// their products.  Both stages are double buffered (136 KB), so one barrier
+// per step separates the stores of step j + 1 from the products of step j.
+constexpr int DW_BK = 128, DW_BC = 128, DW_KJ = 32;
+// Fourier stage row: 128 columns + 16 (288 bytes): the four rings a group of
+// 16 lanes reads in one transposing read start 32 bytes apart modulo 128.
+constexpr int DW_XROW = DW_BC + 16;
+
+typedef short i16x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint2 lds_read_tr16(const SHT_LDS void* a) {
+  return __builtin_bit_cast(uint2, __builtin_amdgcn_ds_read_tr16_b64_v4i16((SHT_LDS i16x4*)a));
+}
+
+__device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const WorkItem it,
+                                                        const float* __restrict__ four, float* __restrict__ spec) {
+  constexpr int BK = DW_BK, BC = DW_BC, KJ = DW_KJ, XROW = DW_XROW;
+  constexpr int NCH = BK / KCH;                 // table chunks per parity (16)
+  constexpr int TS = 2 * 2 * NCH * KJ;          // 16-byte units of a table stage
+  constexpr int XS = 2 * 2 * KJ * XROW / 8;     // 16-byte units of a Fourier stage
+  static_assert(KJ == 32 && NCH == 16 && BC == 128, "tile shape");
+  __shared__ __align__(16) uint4 smem[2 * TS + 2 * XS];  // 136 KB
+
+  const MInfo mi = gload(p.ms + it.m);
+  const int m = mi.m;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nj = (mi.L + KJ - 1) / KJ;
+
+  // Table copies: wave w fills (parity, plane) = w >> 1, chunk pairs
+  // 4 (w & 1) .. + 3 of a stage, one 1 KB instruction per pair (64 lanes x
+  // 16 bytes: 2 chunks x 32 rings).  In the stage, ring r of chunk c sits at
+  // position r ^ (4 (c & 1)) (chosen through the source address), so that
+  // the transposing reads, which take 4 rings of two neighbouring chunks,
+  // cover all banks.  Reads past the padded k range return zero; steps
+  // never pass Lp (a multiple of the step), and rows in [L, Lp) are zero.
+  const u16* tab = (const u16*)p.tab;
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int cpar = wv >> 2, cpl = (wv >> 1) & 1;
+  const int64_t ctoff = cpar ? mi.toff[1] : mi.toff[0];
+  const int ckp = cpar ? mi.Kp[1] : mi.Kp[0];
+  const __amdgpu_buffer_rsrc_t trs =
+      buffer_rsrc_uniform(tab + (cpl ? p.tab_plane : 0) + ctoff, (uint64_t)ckp * mi.Lp * 2);
+  const int lc = lane >> 5;                       // chunk of the pair
+  const int lring = (lane & 31) ^ (4 * lc);       // ring stored at this lane's position
+  uint32_t t_lane[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int cc = 2 * (4 * (wv & 1) + g) + lc;   // chunk within the tile
+    t_lane[g] = ((uint32_t)(it.t0 / KCH + cc) * mi.Lp + (uint32_t)lring) * (KCH * 2);
+  }
+  auto fetch_table = [&](int jc, int stage) {
+    const uint32_t so = __builtin_amdgcn_readfirstlane((uint32_t)jc * KJ * (KCH * 2));
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int pr = 4 * (wv & 1) + g;
+      SHT_LDS void* dst = (SHT_LDS void*)(smem + stage * TS + ((cpar * 2 + cpl) * NCH + 2 * pr) * KJ);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(trs, dst, 16, t_lane[g], so, 0, 0);
+    }
+  };
+
+  // Fourier rows: thread (rp, cq) loads the N and S' rows of rings 2 rp and
+  // 2 rp + 1 of the step at columns 4 cq .. + 3 (the column quad fastest:
+  // a load instruction covers two 512-byte row segments).  Rings past L are
+  // read at ring L - 1 (their table rows are zero); columns past the row end
+  // (outputs never stored) are clamped into the row.
+  const int64_t rowlen = 2 * (int64_t)p.Fp;
+  const int x_cq = tid & 31, x_rp = tid >> 5;
+  const int x_c = min(it.c0 + 4 * x_cq, 2 * p.Fp - 4);
+  int64_t fr[2], fr_next[2];
+  auto fetch_rows = [&](int jc, int64_t* dst) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int r = min(jc * KJ + 2 * x_rp + e, mi.L - 1);
+      dst[e] = gload(&p.rings[mi.first_ring + r].frow);
+    }
+  };
+  float4 rx[2][2];  // [ring][N, S']
+  auto fetch_x = [&]() {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const float* row = four + ((fr[e] + m) * 2) * rowlen + x_c;
+      rx[e][0] = gload((const float4*)row);
+      rx[e][1] = gload((const float4*)(row + rowlen));
+    }
+  };
+
+  // operand reads.  Table (B operand, column k): lane (g = lane / 16,
+  // i = lane % 16) addresses ring 8 (g >> 1) + 4 (h ^ (q >> 1)) + t of chunk
+  // 2 (g & 1) + (q >> 1), bytes 8 (q & 1) of the unit, with t = i / 4,
+  // q = i % 4, for the two reads h = 0, 1 of a fragment (rings 0..3 and
+  // 4..7 of the lane's 8).  Fourier (A operand, column c): ring
+  // 8 (g >> 1) + 4 h + t, column 16 (g & 1) + 4 q.
+  const int par = wave >> 2, kh = (wave >> 1) & 1, chh = wave & 1;
+  const int g = lane >> 4, li = lane & 15, lt = li >> 2, lq = li & 3;
+  uint32_t tb[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+    tb[h] = (uint32_t)(((2 * (g & 1) + (lq >> 1)) * KJ + 8 * (g >> 1) + 4 * (h ^ (lq >> 1)) + lt) * 16 +
+                       8 * (lq & 1));
+  const uint32_t xb = (uint32_t)(((8 * (g >> 1) + lt) * XROW + 16 * (g & 1) + 4 * lq) * 2);
+  const bool live = it.t0 + 64 * kh < (par ? mi.K[1] : mi.K[0]);
+
+  f32x16 acc[2][2];  // [column block][k block]
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x16{};
+
+  fetch_rows(0, fr);
+  fetch_table(0, 0);
+  fetch_x();
+  if (nj > 1) fetch_rows(1, fr_next);
+  for (int jc = 0; jc < nj; ++jc) {
+    const int st = jc & 1;
+    // S = N + S', A = N - S' for 2 rings x 4 columns, split, one 8-byte
+    // store per (ring, S/A, plane)
+    {
+      u16* Xs = (u16*)(smem + 2 * TS + st * XS);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float4 n = rx[e][0], q = rx[e][1];
+#pragma unroll
+        for (int sa = 0; sa < 2; ++sa) {
+          const float4 x = sa ? make_float4(n.x - q.x, n.y - q.y, n.z - q.z, n.w - q.w)
+                              : make_float4(n.x + q.x, n.y + q.y, n.z + q.z, n.w + q.w);
+          uint32_t h0, l0, h1, l1;
+          split2_bf16(x.x, x.y, &h0, &l0);
+          split2_bf16(x.z, x.w, &h1, &l1);
+          const int row = 2 * x_rp + e;
+          lstore((uint2*)(Xs + ((sa * 2 + 0) * KJ + row) * XROW + 4 * x_cq), make_uint2(h0, h1));
+          lstore((uint2*)(Xs + ((sa * 2 + 1) * KJ + row) * XROW + 4 * x_cq), make_uint2(l0, l1));
+        }
+      }
+    }
+    // this step's table copies (issued a step ago) have landed in every
+    // wave, and every wave's Fourier stores are visible
+    __syncthreads();
+    if (jc + 1 < nj) {
+      fr[0] = fr_next[0];
+      fr[1] = fr_next[1];
+      fetch_table(jc + 1, st ^ 1);
+      fetch_x();
+      if (jc + 2 < nj) fetch_rows(jc + 2, fr_next);
+    }
+    if (live) {
+      const char* Tb = (const char*)(smem + st * TS) + (size_t)((par * 2) * NCH + 8 * kh) * KJ * 16;
+      const char* Xb = (const char*)(smem + 2 * TS + st * XS) + (size_t)(par * 2) * KJ * XROW * 2 + 64 * 2 * chh;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {  // 16 rings per MFMA
+        uint4 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+#pragma unroll
+          for (int pl = 0; pl < 2; ++pl) {
+            const char* base = Xb + pl * KJ * XROW * 2 + 16 * s * XROW * 2 + 32 * i * 2 + xb;
+            const uint2 lo = lds_read_tr16((const SHT_LDS void*)base);
+            const uint2 hi = lds_read_tr16((const SHT_LDS void*)(base + 4 * XROW * 2));
+            (pl ? al[i] : ah[i]) = make_uint4(lo.x, lo.y, hi.x, hi.y);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+#pragma unroll
+          for (int pl = 0; pl < 2; ++pl) {
+            const char* base = Tb + (size_t)(pl * NCH + 4 * j) * KJ * 16 + 16 * s * 16;
+            const uint2 lo = lds_read_tr16((const SHT_LDS void*)(base + tb[0]));
+            const uint2 hi = lds_read_tr16((const SHT_LDS void*)(base + tb[1]));
+            (pl ? bl[j] : bh[j]) = make_uint4(lo.x, lo.y, hi.x, hi.y);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = mfma32_bf16(al[i], bh[j], acc[i][j]);
+            acc[i][j] = mfma32_bf16(ah[i], bl[j], acc[i][j]);
+            acc[i][j] = mfma32_bf16(ah[i], bh[j], acc[i][j]);
+          }
+      }
+    }
+  }
+  __syncthreads();
+
+  // accumulator element e of lane l: column c = 8 (e / 4) + 4 (l / 32) + e % 4
+  // of the block, k = l % 32: (re, im) pairs in elements (0, 1) and (2, 3)
+  if (!live) return;
+  const int K = par ? mi.K[1] : mi.K[0];
+  const int twoF = 2 * p.F;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int k = it.t0 + 64 * kh + 32 * j + (lane & 31);
+    if (k >= K) continue;
+    float2* dst = (float2*)spec + (mi.spec_off + 2 * k + par);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int e = 0; e < 16; e += 2) {
+        const int c = it.c0 + 64 * chh + 32 * i + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (c < twoF) {
+          float2 v = make_float2(acc[i][j][e], acc[i][j][e + 1]);
+          if (m == 0) v.y = 0.f;
+          gstore(dst + (int64_t)(c >> 1) * p.nspec, v);
+        }
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Kernels: work groups loop over the items (grid stride), each item with its
 // own plan and buffers.
@@ -1176,6 +1399,20 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const De
   }
 }
 
+__global__ __launch_bounds__(512, 1) void legendre_direct_bf16x3_wide_kernel(const DevPlan* __restrict__ plans,
+                                                                          const WorkItem* __restrict__ items,
+                                                                          int nitems, const IoBind* __restrict__ io,
+                                                                          IoBind io0) {
+  for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+    const WorkItem it = gload(items + w);
+    if (it.m < 0) continue;  // empty slot of the work list
+    DevPlan p = gload(plans + it.plan);
+    const IoBind b = io ? gload(io + it.plan) : io0;
+    if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
+    direct_bf16x3_wide_tile(p, it, (const float*)b.ws, (float*)b.spec);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Variants: (synthesis rows BM, columns BN, waves along columns) and
 // (analysis columns BC, k tile BK, waves along k).
@@ -1194,12 +1431,13 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const De
 #define DIR_F32_C64 legendre_direct_kernel<float, 64, 64, 16, 2>
 #define DIR_F32_C32 legendre_direct_kernel<float, 32, 64, 16, 4>
 #define DIR_BF16 legendre_direct_bf16x3_kernel<128, 64>
+#define DIR_BF16_WIDE legendre_direct_bf16x3_wide_kernel
 
 bool legendre_variant_supported(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C64 || variant == TILE_C32;
   if (prec == SHT_FP32) return variant >= 0 && variant < NUM_TILE_VARIANTS;
   // bf16x3: synthesis 128 x 64 (C64) or 256 x 128 (C128); analysis 64 k x 128
-  // columns in both
+  // columns (C64) or 128 k x 128 columns (C128)
   return variant == TILE_C64 || variant == TILE_C128;
 }
 
@@ -1208,7 +1446,7 @@ void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* di
   *inv_rows = (prec == SHT_FP64) ? 64 : 128;
   *inv_cols = cols;
   if (prec == SHT_BF16X3 && variant == TILE_C128) *inv_rows = 256;
-  *dir_rows = 64;
+  *dir_rows = (prec == SHT_BF16X3 && variant == TILE_C128) ? 128 : 64;
   *dir_cols = (prec == SHT_BF16X3) ? 128 : cols;
 }
 
@@ -1225,13 +1463,13 @@ static const void* inverse_fn(int prec, int variant) {
 }
 
 static int inverse_threads(int prec, int variant) { return (prec == SHT_BF16X3 && variant == TILE_C128) ? 512 : 256; }
-static int direct_threads(int, int) { return 256; }
+static int direct_threads(int prec, int variant) { return (prec == SHT_BF16X3 && variant == TILE_C128) ? 512 : 256; }
 
 static const void* direct_fn(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C32 ? fn(DIR_F64_C32) : fn(DIR_F64_C64);
   if (prec == SHT_FP32)
     return variant == TILE_C128 ? fn(DIR_F32_C128) : variant == TILE_C64 ? fn(DIR_F32_C64) : fn(DIR_F32_C32);
-  return fn(DIR_BF16);
+  return variant == TILE_C128 ? fn(DIR_BF16_WIDE) : fn(DIR_BF16);
 }
 
 int legendre_blocks_per_cu(int prec, int variant, bool inverse) {

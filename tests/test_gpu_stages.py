@@ -160,3 +160,37 @@ def test_legendre_direct(sht, case):
         got = spec_to_complex(spec_t)
         assert rel_l2(got, spec_ref) <= TOL[prec]
         assert np.all(got[:, : N + 1].imag == 0)
+
+
+# bf16x3 analysis with the 128 k x 128 column tile (eight waves, MFMA
+# 32x32x16, transposing LDS reads): k tiles past K for one or both parities,
+# one and several 32-ring steps, column tiles past 2F, m = 0
+@pytest.mark.parametrize("case", WIDE, ids=lambda c: "T%d-%s-F%d" % c)
+def test_legendre_direct_bf16x3_wide_tile(sht, case):
+    N, grid, F = case
+    with sht.Plan(N, grid, F, "bf16x3") as plan:
+        plan.set_tile("c128")
+        assert plan.tile == "c128"
+        geo = oracle.grid_geometry(N, grid)
+        _mu, w = oracle.gauss_newton(geo["nlat"])
+        _g, gnp = grid_inputs(plan, seed=6)
+        chat, spec_ref = oracle.direct(gnp, N, grid)
+        folded = _analysis_form(geo, w, chat).astype(np.complex64).astype(np.complex128)
+        ws = plan.empty_workspace()
+        view = plan.analysis_fourier_view(ws)
+        view.zero_()
+        view[:, :, :F] = torch.from_numpy(folded).to(view.dtype).cuda()
+        print(f"bf16x3 wide analysis T{N} {grid} F={F}", flush=True)
+        spec_t = plan.empty_spec()
+        plan.legendre_direct(ws, spec_t)
+        torch.cuda.synchronize()
+        got = spec_to_complex(spec_t)
+        assert rel_l2(got, spec_ref) <= TOL["bf16x3"]
+        assert np.all(got[:, : N + 1].imag == 0)
+        # the 64 k x 128 column tile sums the same products in another order
+        plan.set_tile("c64")
+        spec2 = plan.empty_spec()
+        plan.legendre_direct(ws, spec2)
+        torch.cuda.synchronize()
+        assert rel_l2(got, spec_to_complex(spec2)) <= 1e-6
+
