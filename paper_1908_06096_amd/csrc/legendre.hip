@@ -1119,8 +1119,13 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
 // their products.  Both stages are double buffered (136 KB), so one barrier
 // per step separates the stores of step j + 1 from the products of step j.
 constexpr int DW_BK = 128, DW_BC = 128, DW_KJ = 32;
-// Fourier stage row: 128 columns + 16 (288 bytes): the four rings a group of
-// 16 lanes reads in one transposing read start 32 bytes apart modulo 128.
+// LDS banks (measured with the bank-conflict counter): the transposing reads
+// of lanes 0..31 (and of 32..63) are served together from 256 bytes (64
+// banks of 4 bytes), 8-byte stores 16 lanes at a time from 128 bytes.
+// Fourier stage row: 128 columns + 16 (288 bytes), with the 16-column
+// blocks b stored at 32 ((b & 1) 4 + b / 2) bytes: a transposing read takes
+// 4 rings of blocks b and b + 1 (b even), which then fall on 8 different
+// 32-byte bank groups (the rings 32 bytes apart, the blocks 128 apart).
 constexpr int DW_XROW = DW_BC + 16;
 
 typedef short i16x4 __attribute__((ext_vector_type(4)));
@@ -1148,9 +1153,9 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
   // Table copies: wave w fills (parity, plane) = w >> 1, chunk pairs
   // 4 (w & 1) .. + 3 of a stage, one 1 KB instruction per pair (64 lanes x
   // 16 bytes: 2 chunks x 32 rings).  In the stage, ring r of chunk c sits at
-  // position r ^ (4 (c & 1)) (chosen through the source address), so that
-  // the transposing reads, which take 4 rings of two neighbouring chunks,
-  // cover all banks.  Reads past the padded k range return zero; steps
+  // position r ^ (4 (c & 1)) ^ (8 ((c >> 1) & 1)) (chosen through the source
+  // address), so that the transposing reads of 32 lanes, which take 4 rings
+  // of four consecutive chunks, cover all banks.  Reads past the padded k range return zero; steps
   // never pass Lp (a multiple of the step), and rows in [L, Lp) are zero.
   const u16* tab = (const u16*)p.tab;
   const int wv = __builtin_amdgcn_readfirstlane(wave);
@@ -1160,11 +1165,11 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
   const __amdgpu_buffer_rsrc_t trs =
       buffer_rsrc_uniform(tab + (cpl ? p.tab_plane : 0) + ctoff, (uint64_t)ckp * mi.Lp * 2);
   const int lc = lane >> 5;                       // chunk of the pair
-  const int lring = (lane & 31) ^ (4 * lc);       // ring stored at this lane's position
   uint32_t t_lane[4];
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
     const int cc = 2 * (4 * (wv & 1) + g) + lc;   // chunk within the tile
+    const int lring = (lane & 31) ^ (4 * lc) ^ (8 * (g & 1));  // ring stored at this lane's position
     t_lane[g] = ((uint32_t)(it.t0 / KCH + cc) * mi.Lp + (uint32_t)lring) * (KCH * 2);
   }
   auto fetch_table = [&](int jc, int stage) {
@@ -1177,13 +1182,17 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
     }
   };
 
-  // Fourier rows: thread (rp, cq) loads the N and S' rows of rings 2 rp and
-  // 2 rp + 1 of the step at columns 4 cq .. + 3 (the column quad fastest:
-  // a load instruction covers two 512-byte row segments).  Rings past L are
-  // read at ring L - 1 (their table rows are zero); columns past the row end
-  // (outputs never stored) are clamped into the row.
+  // Fourier rows: thread (rp, pos) loads the N and S' rows of rings 2 rp and
+  // 2 rp + 1 of the step at the column quad cq whose stage place is 4 pos
+  // (columns 4 cq .. + 3 are stored at 4 pos .. + 3 of the row), so that the
+  // stores of consecutive lanes are contiguous; a load instruction still
+  // covers two 512-byte row segments.  Rings past L are read at ring L - 1
+  // (their table rows are zero); columns past the row end (outputs never
+  // stored) are clamped into the row.
   const int64_t rowlen = 2 * (int64_t)p.Fp;
-  const int x_cq = tid & 31, x_rp = tid >> 5;
+  const int x_pos = tid & 31, x_rp = tid >> 5;
+  const int x_bp = x_pos >> 2;
+  const int x_cq = 4 * (x_bp < 4 ? 2 * x_bp : 2 * x_bp - 7) + (x_pos & 3);
   const int x_c = min(it.c0 + 4 * x_cq, 2 * p.Fp - 4);
   int64_t fr[2], fr_next[2];
   auto fetch_rows = [&](int jc, int64_t* dst) {
@@ -1204,19 +1213,22 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
   };
 
   // operand reads.  Table (B operand, column k): lane (g = lane / 16,
-  // i = lane % 16) addresses ring 8 (g >> 1) + 4 (h ^ (q >> 1)) + t of chunk
-  // 2 (g & 1) + (q >> 1), bytes 8 (q & 1) of the unit, with t = i / 4,
-  // q = i % 4, for the two reads h = 0, 1 of a fragment (rings 0..3 and
-  // 4..7 of the lane's 8).  Fourier (A operand, column c): ring
-  // 8 (g >> 1) + 4 h + t, column 16 (g & 1) + 4 q.
+  // i = lane % 16) addresses ring 8 (g >> 1) + 4 h + t of chunk
+  // 2 (g & 1) + (q >> 1), at position ring ^ 4 (q >> 1) ^ 8 (g & 1), bytes
+  // 8 (q & 1) of the unit, with t = i / 4, q = i % 4, for the two reads
+  // h = 0, 1 of a fragment (rings 0..3 and 4..7 of the lane's 8).  Fourier
+  // (A operand, column c): ring 8 (g >> 1) + 4 h + t, column
+  // 64 chh + 32 i + 16 (g & 1) + 4 q, whose 16-column block 4 chh + 2 i +
+  // (g & 1) sits at 32 (4 (g & 1) + 2 chh + i) bytes of the row.
   const int par = wave >> 2, kh = (wave >> 1) & 1, chh = wave & 1;
   const int g = lane >> 4, li = lane & 15, lt = li >> 2, lq = li & 3;
   uint32_t tb[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
-    tb[h] = (uint32_t)(((2 * (g & 1) + (lq >> 1)) * KJ + 8 * (g >> 1) + 4 * (h ^ (lq >> 1)) + lt) * 16 +
+    tb[h] = (uint32_t)(((2 * (g & 1) + (lq >> 1)) * KJ +
+                        ((8 * (g >> 1) + 4 * h + lt) ^ (4 * (lq >> 1)) ^ (8 * (g & 1)))) * 16 +
                        8 * (lq & 1));
-  const uint32_t xb = (uint32_t)(((8 * (g >> 1) + lt) * XROW + 16 * (g & 1) + 4 * lq) * 2);
+  const uint32_t xb = (uint32_t)(((8 * (g >> 1) + lt) * XROW + 64 * (g & 1) + 4 * lq) * 2);
   const bool live = it.t0 + 64 * kh < (par ? mi.K[1] : mi.K[0]);
 
   f32x16 acc[2][2];  // [column block][k block]
@@ -1246,8 +1258,8 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
           split2_bf16(x.x, x.y, &h0, &l0);
           split2_bf16(x.z, x.w, &h1, &l1);
           const int row = 2 * x_rp + e;
-          lstore((uint2*)(Xs + ((sa * 2 + 0) * KJ + row) * XROW + 4 * x_cq), make_uint2(h0, h1));
-          lstore((uint2*)(Xs + ((sa * 2 + 1) * KJ + row) * XROW + 4 * x_cq), make_uint2(l0, l1));
+          lstore((uint2*)(Xs + ((sa * 2 + 0) * KJ + row) * XROW + 4 * x_pos), make_uint2(h0, h1));
+          lstore((uint2*)(Xs + ((sa * 2 + 1) * KJ + row) * XROW + 4 * x_pos), make_uint2(l0, l1));
         }
       }
     }
@@ -1263,7 +1275,7 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
     }
     if (live) {
       const char* Tb = (const char*)(smem + st * TS) + (size_t)((par * 2) * NCH + 8 * kh) * KJ * 16;
-      const char* Xb = (const char*)(smem + 2 * TS + st * XS) + (size_t)(par * 2) * KJ * XROW * 2 + 64 * 2 * chh;
+      const char* Xb = (const char*)(smem + 2 * TS + st * XS) + (size_t)(par * 2) * KJ * XROW * 2 + 2 * 16 * 2 * chh;
 #pragma unroll
       for (int s = 0; s < 2; ++s) {  // 16 rings per MFMA
         uint4 ah[2], al[2], bh[2], bl[2];
@@ -1271,7 +1283,7 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
         for (int i = 0; i < 2; ++i) {
 #pragma unroll
           for (int pl = 0; pl < 2; ++pl) {
-            const char* base = Xb + pl * KJ * XROW * 2 + 16 * s * XROW * 2 + 32 * i * 2 + xb;
+            const char* base = Xb + pl * KJ * XROW * 2 + 16 * s * XROW * 2 + 16 * i * 2 + xb;
             const uint2 lo = lds_read_tr16((const SHT_LDS void*)base);
             const uint2 hi = lds_read_tr16((const SHT_LDS void*)(base + 4 * XROW * 2));
             (pl ? al[i] : ah[i]) = make_uint4(lo.x, lo.y, hi.x, hi.y);
