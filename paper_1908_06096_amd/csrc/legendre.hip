@@ -738,16 +738,23 @@ __device__ inline f32x16 mfma32_bf16(const uint4& a, const uint4& b, f32x16 c) {
                                                  0, 0, 0);
 }
 
-constexpr int BW_BM = 256, BW_BN = 128, BW_KI = 16;
+constexpr int BW_BN = 128, BW_KI = 16;
+// waves of the wide synthesis work group (rows = 32 per wave)
+#ifndef SHT_BW_WAVES
+#define SHT_BW_WAVES 4
+#endif
+constexpr int BW_WAVES = SHT_BW_WAVES;
 
+template <int NW>
 __device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const WorkItem it,
                                                          const float* __restrict__ spec, float* __restrict__ four) {
-  constexpr int BM = BW_BM, BN = BW_BN, KI = BW_KI;
+  constexpr int BM = 32 * NW, BN = BW_BN, KI = BW_KI;
+  constexpr int NT = 64 * NW;
   constexpr int NCK = KI / KCH;         // k chunks per parity per step (2)
   constexpr int AS = 2 * 2 * NCK * BM;  // 16-byte units of one table stage
   constexpr int BS = 2 * 2 * NCK * BN;  // 16-byte units of one spectral stage
-  static_assert(NCK == 2 && BM == 256 && BN == 128, "tile shape");
-  __shared__ __align__(16) uint4 smem[2 * AS + 2 * BS];  // 96 KB
+  static_assert(NCK == 2 && (NW == 4 || NW == 8) && BN == 128, "tile shape");
+  __shared__ __align__(16) uint4 smem[2 * AS + 2 * BS];  // 64 KB (4 waves) or 96 KB (8 waves)
 
   const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
@@ -758,14 +765,16 @@ __device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const
   const int kpmax = mi.Kp[0] > mi.Kp[1] ? mi.Kp[0] : mi.Kp[1];
   const int nk = (kpmax + KI - 1) / KI;
 
-  // Table copies: wave w fills (parity, plane) = w / 2, chunk w % 2 of a
-  // stage, four 64-row groups of 1 KB (64 lanes x 16 bytes, contiguous in
-  // the chunk-major table).  Reads past the table's padded k range return
+  // Table copies: a stage is 8 (parity, plane, chunk) slices of BM rows, in
+  // 64-row groups of 1 KB (64 lanes x 16 bytes, contiguous in the
+  // chunk-major table); each wave copies four groups, of 8 / NW slices that
+  // share a parity and plane.  Reads past the table's padded k range return
   // zero; rows past Lp read the next chunk's rows and only feed rows past L,
   // whose outputs are never stored.
+  constexpr int RG = BM / 64, CPW = 8 / NW;  // row groups per slice, slices per wave
   const u16* tab = (const u16*)p.tab;
   const int wv = __builtin_amdgcn_readfirstlane(wave);
-  const int cpar = wv >> 2, cpl = (wv >> 1) & 1, cch = wv & 1;
+  const int cpar = (wv * CPW) >> 2, cpl = ((wv * CPW) >> 1) & 1;
   // (selects rather than indexing mi.toff / mi.Kp with a variable, which
   // would put a copy of mi in memory)
   const int64_t ctoff = cpar ? mi.toff[1] : mi.toff[0];
@@ -773,33 +782,36 @@ __device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const
   const __amdgpu_buffer_rsrc_t tr =
       buffer_rsrc_uniform(tab + (cpl ? p.tab_plane : 0) + ctoff, (uint64_t)ckp * mi.Lp * 2);
   const uint32_t a_step = __builtin_amdgcn_readfirstlane((uint32_t)NCK * mi.Lp * KCH * 2);
-  const uint32_t t_lane = ((uint32_t)(it.t0 + lane) + (uint32_t)cch * mi.Lp) * KCH * 2;
   auto fetch_table = [&](int kc, int stage) {
     const uint32_t sa = (uint32_t)kc * a_step;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
-      SHT_LDS void* dst = (SHT_LDS void*)(smem + stage * AS + ((cpar * 2 + cpl) * NCK + cch) * BM + 64 * g);
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(tr, dst, 16, t_lane + (uint32_t)(64 * g) * KCH * 2, sa, 0, 0);
+      const int slice = wv * CPW + g / RG, rg = g % RG, cch = slice & 1;
+      SHT_LDS void* dst = (SHT_LDS void*)(smem + stage * AS + slice * BM + 64 * rg);
+      const uint32_t t_lane = ((uint32_t)(it.t0 + 64 * rg + lane) + (uint32_t)cch * mi.Lp) * KCH * 2;
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(tr, dst, 16, t_lane, sa, 0, 0);
     }
   };
-  // Spectral values: thread (fi, sg) loads n - m = 32 kc + 4 sg .. + 3 of
-  // field f0 + fi (32 bytes); the field index is clamped to F - 1 (fields
-  // past F only feed outputs never stored) and values read past n = N meet
-  // zero table entries.
-  const int fi = tid >> 3, sg = tid & 7;
+  // Spectral values: thread (fi, sg) loads n - m = 32 kc + 4 (U sg + u) .. + 3
+  // (u < U) of field f0 + fi (16 bytes each); the field index is clamped to
+  // F - 1 (fields past F only feed outputs never stored) and values read
+  // past n = N meet zero table entries.
+  constexpr int SGN = NT / 64, U = 8 / SGN;  // segments per field, 4-n units per thread
+  const int fi = tid / SGN, sg = tid % SGN;
   const int f0 = it.c0 / 2;
   const int f = f0 + fi;
   const uint32_t fl = (uint32_t)((f < p.F ? f : p.F - 1) - f0);
   const int64_t sbase = (int64_t)f0 * p.nspec + mi.spec_off;
   const __amdgpu_buffer_rsrc_t sr =
       buffer_rsrc_uniform((const float2*)spec + sbase, (uint64_t)((int64_t)p.F * p.nspec - sbase) * 8u);
-  const uint32_t b_off = (fl * (uint32_t)p.nspec + 4u * sg) * 8u;
+  const uint32_t b_off = (fl * (uint32_t)p.nspec + 4u * U * sg) * 8u;
   const bool m0 = m == 0;
-  float4 rv[2];
+  float4 rv[2 * U];
   auto fetch_spec = [&](int kc) {
     const uint32_t sb = (uint32_t)kc * (2 * KI * 8);
-    rv[0] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off, sb, 0));
-    rv[1] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off + 16, sb, 0));
+#pragma unroll
+    for (int i = 0; i < 2 * U; ++i)
+      rv[i] = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(sr, b_off + 16 * i, sb, 0));
   };
 
   f32x16 acc[2][2][2];
@@ -815,21 +827,25 @@ __device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const
   for (int kc = 0; kc < nk; ++kc) {
     const int st = kc & 1;
     uint4* Bs = smem + 2 * AS + st * BS;
-    // n - m = 4 sg + q (q < 4): parity q & 1, k = 2 sg + (q >> 1) within the
-    // step, i.e. chunk sg >> 2, bytes 4 (sg & 3) of the unit; Im a_n^0 dropped
-    {
-      const int ch = sg >> 2;
+    // n - m = 4 s + q (q < 4, s = U sg + u): parity q & 1, k = 2 s + (q >> 1)
+    // within the step, i.e. chunk s >> 2, bytes 4 (s & 3) of the unit; Im a_n^0
+    // dropped
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int su = U * sg + u;
+      const int ch = su >> 2;
+      const float4 r0 = rv[2 * u], r1 = rv[2 * u + 1];
 #pragma unroll
       for (int pa = 0; pa < 2; ++pa) {
 #pragma unroll
         for (int comp = 0; comp < 2; ++comp) {
-          const float x0 = pa ? (comp ? rv[0].w : rv[0].z) : (comp ? rv[0].y : rv[0].x);
-          const float x1 = pa ? (comp ? rv[1].w : rv[1].z) : (comp ? rv[1].y : rv[1].x);
+          const float x0 = pa ? (comp ? r0.w : r0.z) : (comp ? r0.y : r0.x);
+          const float x1 = pa ? (comp ? r1.w : r1.z) : (comp ? r1.y : r1.x);
           uint32_t h, l;
           split2_bf16((comp && m0) ? 0.f : x0, (comp && m0) ? 0.f : x1, &h, &l);
           const int col = (2 * fi + comp) ^ ch;
-          uint32_t* dh = (uint32_t*)(Bs + ((pa * 2 + 0) * NCK + ch) * BN + col) + (sg & 3);
-          uint32_t* dl = (uint32_t*)(Bs + ((pa * 2 + 1) * NCK + ch) * BN + col) + (sg & 3);
+          uint32_t* dh = (uint32_t*)(Bs + ((pa * 2 + 0) * NCK + ch) * BN + col) + (su & 3);
+          uint32_t* dl = (uint32_t*)(Bs + ((pa * 2 + 1) * NCK + ch) * BN + col) + (su & 3);
           *dh = h;
           *dl = l;
         }
@@ -873,7 +889,7 @@ __device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const
 
   // epilogue: Fourier row offsets of the tile's rings and their mirrors
   // through LDS, then north = S + A and south = S - A from the registers
-  int64_t* roff = (int64_t*)smem;  // [256][2]
+  int64_t* roff = (int64_t*)smem;  // [BM][2]
   const int64_t rowlen = 2 * (int64_t)p.Fp;
   if (tid < BM) {
     const int row = it.t0 + tid;
@@ -1383,17 +1399,16 @@ __global__ __launch_bounds__(256, 2) void legendre_inverse_bf16x3_kernel(const D
   }
 }
 
-__global__ __launch_bounds__(512, 1) void legendre_inverse_bf16x3_wide_kernel(const DevPlan* __restrict__ plans,
-                                                                           const WorkItem* __restrict__ items,
-                                                                           int nitems, const IoBind* __restrict__ io,
-                                                                           IoBind io0) {
+__global__ __launch_bounds__(64 * BW_WAVES, BW_WAVES == 4 ? 2 : 1) void legendre_inverse_bf16x3_wide_kernel(
+    const DevPlan* __restrict__ plans, const WorkItem* __restrict__ items, int nitems, const IoBind* __restrict__ io,
+    IoBind io0) {
   for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
     const WorkItem it = gload(items + w);
     if (it.m < 0) continue;  // empty slot of the work list
     DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
-    inverse_bf16x3_wide_tile(p, it, (const float*)b.spec, (float*)b.ws);
+    inverse_bf16x3_wide_tile<BW_WAVES>(p, it, (const float*)b.spec, (float*)b.ws);
   }
 }
 
@@ -1457,7 +1472,7 @@ void legendre_tiles(int prec, int variant, int* inv_rows, int* inv_cols, int* di
   const int cols = variant == TILE_C128 ? 128 : variant == TILE_C64 ? 64 : 32;
   *inv_rows = (prec == SHT_FP64) ? 64 : 128;
   *inv_cols = cols;
-  if (prec == SHT_BF16X3 && variant == TILE_C128) *inv_rows = 256;
+  if (prec == SHT_BF16X3 && variant == TILE_C128) *inv_rows = 32 * BW_WAVES;
   *dir_rows = (prec == SHT_BF16X3 && variant == TILE_C128) ? 128 : 64;
   *dir_cols = (prec == SHT_BF16X3) ? 128 : cols;
 }
@@ -1474,7 +1489,9 @@ static const void* inverse_fn(int prec, int variant) {
   return variant == TILE_C128 ? fn(INV_BF16_WIDE) : fn(INV_BF16);
 }
 
-static int inverse_threads(int prec, int variant) { return (prec == SHT_BF16X3 && variant == TILE_C128) ? 512 : 256; }
+static int inverse_threads(int prec, int variant) {
+  return (prec == SHT_BF16X3 && variant == TILE_C128) ? 64 * BW_WAVES : 256;
+}
 static int direct_threads(int prec, int variant) { return (prec == SHT_BF16X3 && variant == TILE_C128) ? 512 : 256; }
 
 static const void* direct_fn(int prec, int variant) {
