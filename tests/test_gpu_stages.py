@@ -50,7 +50,7 @@ def test_legendre_inverse(sht, case):
         assert rel_l2(got, four) <= TOL[prec]
 
 
-# bf16x3 synthesis with the 256 x 128 tile (eight waves, MFMA 32x32x16):
+# bf16x3 synthesis with the 128 x 128 tile (four waves, MFMA 32x32x16):
 # ragged row tiles (L not a multiple of 256), column tiles past 2F, one and
 # several k steps, m = 0
 WIDE = [(31, "full", 1), (47, "octahedral", 33), (95, "octahedral", 70), (159, "octahedral", 5),
@@ -71,7 +71,8 @@ def test_legendre_inverse_bf16x3_wide_tile(sht, case):
         got = plan.synthesis_fourier_view(ws)[:, :F].cpu().numpy().T
         four, _g = oracle.inverse(spec_c, N, grid)
         assert rel_l2(got, four) <= TOL["bf16x3"]
-        # the same coefficients through the 128 x 64 tile agree to the split's rounding
+        # the same coefficients through the 128 x 64 tile (MFMA 16x16x32) agree
+        # to the split's rounding
         plan.set_tile("c64")
         ws2 = plan.empty_workspace()
         plan.legendre_inverse(spec_t, ws2)
