@@ -52,20 +52,23 @@ __device__ inline C cscale(C a, T s) {
 // LDS layout of the transforms.  The FFT kernels have no LDS but their
 // dynamic buffer, which therefore starts at LDS address 0 (checked on the
 // host).  Element y of that buffer, counted over the whole work group,
-// sits in slot y + y / 32: one spare slot after every 32 elements.  The
+// sits in slot y + (y >> S): one spare slot after every 2^S elements.  The
 // early Stockham passes write with a lane stride of R elements (R Ns with
 // Ns < 64), which unpadded would put most lanes of a wave on the same
-// banks; the spare slots spread them.  Field s of a work group owns the
-// elements [s fs, s fs + L), fs = lds_stride(L) a multiple of 32, so the byte
-// address of any element is (y + (y >> 5)) * sizeof(C), two instructions
-// from its index.
-constexpr int FFT_PAD_SHIFT = 5;
+// banks; the spare slots spread them.  S is 3 for 8-byte elements (FP32
+// complex) and 5 for 16-byte ones (FP64): measured over the TCo1279 stages,
+// FP32 spacings of 8, 16 and 32 elements took 16.6, 17.6 and 17.2 ms per
+// synthesis (4: 17.6), FP64 spacings of 8, 16 and 32 took 39.5, 40.2 and
+// 39.3 ms.  Field s of a work group owns the elements [s fs, s fs + L),
+// fs = lds_stride(L) a multiple of 32, so the byte address of any element
+// is (y + (y >> S)) * sizeof(C), two instructions from its index.
+__host__ __device__ constexpr int fft_pad_shift(size_t elem) { return elem == 8 ? 3 : 5; }
 __host__ __device__ constexpr uint32_t lds_stride(int L) { return ((uint32_t)L + 31u) & ~31u; }
 // slots that hold the elements [0, n)
-__host__ __device__ constexpr size_t lds_slots(size_t n) { return n + (n >> FFT_PAD_SHIFT) + 1; }
+__host__ __device__ constexpr size_t lds_slots(size_t n, size_t elem) { return n + (n >> fft_pad_shift(elem)) + 1; }
 template <typename C>
 __device__ __forceinline__ SHT_LDS C* lds_elem(uint32_t y) {
-  return (SHT_LDS C*)((y + (y >> FFT_PAD_SHIFT)) * (uint32_t)sizeof(C));
+  return (SHT_LDS C*)((y + (y >> fft_pad_shift(sizeof(C)))) * (uint32_t)sizeof(C));
 }
 
 // 8- and 16-byte values in LDS through an address-space-3 pointer (32-bit
@@ -796,7 +799,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
 
 size_t fft_lds_bytes(int prec, int L, int G) {
   const size_t c = (prec == SHT_FP64) ? 16 : 8;
-  return c * lds_slots((size_t)G * lds_stride(L));
+  return c * lds_slots((size_t)G * lds_stride(L), c);
 }
 
 // Kernels: work groups loop over the items (grid stride), one kernel per

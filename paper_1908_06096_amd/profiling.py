@@ -4,13 +4,17 @@
     python -m paper_1908_06096_amd.profiling traffic <fetch_counter_collection.csv> \
         <write_counter_collection.csv> <copy_bytes> <out.json> "<commands>"
     python -m paper_1908_06096_amd.profiling sq <counter_collection.csv> <out.md> "<command>"
+    python -m paper_1908_06096_amd.profiling lds <counter_collection.csv> <out.md> "<command>"
 
 ``stats`` turns a ``--kernel-trace --stats`` summary into a short markdown
 table.  ``sq`` summarises an SQ/GRBM counter run per kernel: MFMA pipe busy
 (SQ_VALU_MFMA_BUSY_CYCLES over the active cycles of all 1024 SIMDs; the
 GRBM_GUI_ACTIVE reading is the sum over the 8 XCDs), the MFMA work issued
 (SQ_INSTS_VALU_MFMA_MOPS_* x 512 flops) and VALU issue (SQ_INSTS_VALU, a
-wave64 instruction holding a SIMD for 4 cycles).  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
+wave64 instruction holding a SIMD for 4 cycles).  ``lds`` summarises an LDS
+counter run: bank-conflict cycles against the cycles LDS instructions were
+active, LDS instructions issued, wave-cycles spent waiting on LDS, and MFMA
+busy as in ``sq``.  ``traffic`` turns two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE``
 runs into HBM bytes per dispatch for each kernel, scaled by what the same
 counters read for a plain device copy of ``copy_bytes`` bytes captured in the
 same runs (the runtime's ``copyBuffer`` dispatch whose write counter is the
@@ -190,6 +194,48 @@ def measured_traffic(path, stage):
     return k["fetch_bytes"] + k["write_bytes"]
 
 
+def lds_markdown(csv_path, out_md, command):
+    per = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(dict)
+    for r in csv.DictReader(open(csv_path)):
+        k = _short(r["Kernel_Name"])
+        per[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        dur[k][r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+    lines = [
+        "# LDS counters per kernel (averages per dispatch)",
+        "",
+        "Command:",
+        "",
+        "```",
+        command,
+        "```",
+        "",
+        "Bank-conflict cycles (SQ_LDS_BANK_CONFLICT) against the cycles LDS instructions were active "
+        "(SQ_ACTIVE_INST_LDS), LDS instructions (SQ_INSTS_LDS), wave-cycles waiting on LDS (SQ_WAIT_INST_LDS); "
+        "MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 x 1024 SIMDs).",
+        "",
+        "| kernel | dispatches | ms | bank-conflict cycles | LDS active cycles | LDS instr | LDS wait | MFMA busy |",
+        "|---|---|---|---|---|---|---|---|",
+    ]
+    for k in sorted(per, key=lambda x: -sum(dur[x].values())):
+        c = per[k]
+        if "legendre" not in k and "fourier" not in k:
+            continue
+
+        def avg(name):
+            v = c.get(name, [0.0])
+            return sum(v) / len(v)
+
+        active = avg("GRBM_GUI_ACTIVE") / XCDS * SIMDS
+        mfma = avg("SQ_VALU_MFMA_BUSY_CYCLES") / active if active else 0.0
+        ms = sum(dur[k].values()) / len(dur[k])
+        lines.append("| `%s` | %d | %.3f | %.3g | %.3g | %.3g | %.3g | %.1f%% |" % (
+            k, len(dur[k]), ms, avg("SQ_LDS_BANK_CONFLICT"), avg("SQ_ACTIVE_INST_LDS"), avg("SQ_INSTS_LDS"),
+            avg("SQ_WAIT_INST_LDS"), 100 * mfma))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
@@ -197,5 +243,7 @@ if __name__ == "__main__":
         traffic_json(sys.argv[2], sys.argv[3], float(sys.argv[4]), sys.argv[5], sys.argv[6])
     elif sys.argv[1] == "sq":
         sq_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
+    elif sys.argv[1] == "lds":
+        lds_markdown(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
         raise SystemExit(__doc__)
