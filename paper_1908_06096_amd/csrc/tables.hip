@@ -256,16 +256,24 @@ hipError_t launch_table_export_planes(const DevPlan& p, int prec, const MInfo& m
 }
 
 // ---------------------------------------------------------------------------
-// FFT tables, one work group per class.  Angles are reduced exactly in
-// integer arithmetic before one float64 sincospi call:
+// FFT tables.  fft_tables_kernel, one work group per class, reduces each
+// angle exactly in integer arithmetic before one float64 sincospi call:
 //   twiddles, pass after pass (radix R after Ns points are combined):
 //          exp(-2 pi i r k / (Ns R))             k < Ns, 1 <= r < R
 //   post   exp(-2 pi i q / (2h))                   q < h
 //   chirp  exp(-i pi (t^2 mod 2h) / h)             t < h
-//   khat_u = (1/L) sum_{|t| < h} exp(+i pi t^2/h) exp(-2 pi i u t / L)
-// khat is the length-L DFT of the conjugate chirp wrapped around zero, i.e.
-// the kernel of the chirp-z (Bluestein) convolution, with the 1/L of the
-// inverse DFT folded in.
+// khat_kernel makes the chirp-z (Bluestein) convolution kernel, the
+// length-L DFT of the conjugate chirp wrapped around zero with the 1/L of
+// the inverse DFT folded in:
+//   khat_u = (1/L) sum_{|t| < h} c_t exp(-2 pi i u t / L),  c_t = exp(i pi t^2 / h).
+// c_t is even in t, so the terms t and -t pair into a real cosine:
+//   khat_u = (1/L) (1 + 2 sum_{t=1}^{h-1} c_t cos(2 pi j / L)),  j = u t mod L,
+// with j advanced by u per term and cos(2 pi j / L) = Re(W_hi[j >> 8] W_lo[j & 255])
+// from two float64 tables of unit roots exp(-2 pi i j / L) in LDS; c_t comes
+// in chunks of KH_CHUNK from sincospi of (t^2 mod 2h) / h.  Every value is
+// formed in float64 (about three roundings per term against one for a
+// sincospi per term, which cost an int64 remainder each and made the kernel
+// 40 to 80 times slower).
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -305,32 +313,78 @@ __global__ void fft_tables_kernel(const FftClass* cls, T* fft) {
     sincospi(-(double)r / (double)h, &sn, &cs);
     put_c(fft, c.chirp_off + t, cs, sn);
   }
-  // khat: phase of term t is pi (t^2 L - 2 u t h) / (h L), reduced mod 2 h L
-  const int64_t hl = (int64_t)h * L;
-  for (int u = threadIdx.x; u < L; u += blockDim.x) {
-    double re = 0.0, im = 0.0;
-    for (int t = -(h - 1); t <= h - 1; ++t) {
-      int64_t num = ((int64_t)t * t) * L - 2 * (int64_t)u * t * h;
-      num %= 2 * hl;
-      if (num < 0) num += 2 * hl;
-      double sn, cs;
-      sincospi((double)num / (double)hl, &sn, &cs);
-      re += cs;
-      im += sn;
-    }
-    put_c(fft, c.khat_off + u, re / L, im / L);
+}
+
+constexpr int KH_THREADS = 256, KH_LO = 256, KH_HI = 512, KH_CHUNK = 512;
+// lengths the two root tables cover
+constexpr int64_t KH_MAX_L = (int64_t)KH_LO * KH_HI;
+
+// block (x, class): u = x KH_THREADS + thread
+template <typename T>
+__global__ void khat_kernel(const FftClass* cls, T* fft) {
+  const FftClass c = cls[blockIdx.y];
+  if (!c.bluestein) return;
+  const int L = c.L, h = c.h;
+  const int u0 = blockIdx.x * KH_THREADS;
+  if (u0 >= L) return;
+  __shared__ double2 wlo[KH_LO], whi[KH_HI], ct[KH_CHUNK];
+  const int nhi = (L + KH_LO - 1) / KH_LO;
+  for (int j = threadIdx.x; j < KH_LO; j += KH_THREADS) {
+    double sn, cs;
+    sincospi(-2.0 * (double)j / (double)L, &sn, &cs);
+    wlo[j] = make_double2(cs, sn);
   }
+  for (int j = threadIdx.x; j < nhi; j += KH_THREADS) {
+    double sn, cs;
+    sincospi(-2.0 * (double)(((int64_t)j * KH_LO) % L) / (double)L, &sn, &cs);
+    whi[j] = make_double2(cs, sn);
+  }
+  const int u = u0 + threadIdx.x;
+  double re = 0.0, im = 0.0;
+  int j = 0;  // u t mod L
+  for (int t0 = 1; t0 < h; t0 += KH_CHUNK) {
+    const int n = min(KH_CHUNK, h - t0);
+    __syncthreads();  // the previous chunk is consumed (and the root tables are written)
+    for (int i = threadIdx.x; i < n; i += KH_THREADS) {
+      const int64_t t = t0 + i;
+      double sn, cs;
+      sincospi((double)((t * t) % (2 * (int64_t)h)) / (double)h, &sn, &cs);
+      ct[i] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    if (u < L) {
+      for (int i = 0; i < n; ++i) {
+        j += u;
+        if (j >= L) j -= L;
+        const double2 a = whi[j >> 8], b = wlo[j & (KH_LO - 1)];
+        const double w = a.x * b.x - a.y * b.y;  // cos(2 pi j / L)
+        const double2 cv = ct[i];
+        re = fma(cv.x, w, re);
+        im = fma(cv.y, w, im);
+      }
+    }
+  }
+  if (u < L) put_c(fft, c.khat_off + u, (1.0 + 2.0 * re) / L, (2.0 * im) / L);
 }
 
 hipError_t launch_fft_tables(const DevPlan& p, int prec, const FftClass* d_cls, int ncls,
                              const FftClass* h_cls, void* fft, hipStream_t s) {
   (void)p;
-  (void)h_cls;
   if (ncls == 0) return hipSuccess;
-  if (prec == SHT_FP64)
+  int maxL = 0;
+  for (int i = 0; i < ncls; ++i)
+    if (h_cls[i].bluestein) {
+      if ((int64_t)h_cls[i].L > KH_MAX_L) return hipErrorInvalidValue;
+      maxL = std::max(maxL, h_cls[i].L);
+    }
+  const dim3 kg((unsigned)std::max(1, (maxL + KH_THREADS - 1) / KH_THREADS), (unsigned)ncls);
+  if (prec == SHT_FP64) {
     hipLaunchKernelGGL(fft_tables_kernel<double>, dim3(ncls), dim3(256), 0, s, d_cls, (double*)fft);
-  else
+    if (maxL > 0) hipLaunchKernelGGL(khat_kernel<double>, kg, dim3(KH_THREADS), 0, s, d_cls, (double*)fft);
+  } else {
     hipLaunchKernelGGL(fft_tables_kernel<float>, dim3(ncls), dim3(256), 0, s, d_cls, (float*)fft);
+    if (maxL > 0) hipLaunchKernelGGL(khat_kernel<float>, kg, dim3(KH_THREADS), 0, s, d_cls, (float*)fft);
+  }
   return hipGetLastError();
 }
 
