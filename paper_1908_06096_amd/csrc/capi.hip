@@ -409,9 +409,11 @@ void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
 // FFT_MAX_G) whose threads per field (the tier's work-group size / G) still
 // hold every pass with the same pass count and whose LDS fits the tier's
 // budget, the most LDS that keeps the occupancy the tier's longest class has
-// with G = 1.  The classes come in with the radices for FFT_THREADS threads
-// per field.
-void choose_groups(int prec, std::vector<FftClass>* cls) {
+// with G = 1, and whose fields' rings lie within 2^31 bytes of the first
+// one's (the analysis reads them through one descriptor with 32-bit
+// offsets: (G - 1) npts + 2h grid values).  The classes come in with the
+// radices for FFT_THREADS threads per field.
+void choose_groups(int prec, int64_t npts, std::vector<FftClass>* cls) {
   auto lds = [&](const FftClass& c, int G) { return fft_lds_bytes(prec, c.L, G); };
   for (FftClass& c : *cls) {
     // a prime radix above FFT_BIG_PRIME is always the first pass
@@ -445,6 +447,8 @@ void choose_groups(int prec, std::vector<FftClass>* cls) {
       const std::vector<int> rad = radices(c.L, threads / G, c.bluestein);
       if (rad.empty() || rad.size() > (size_t)c.nrad) break;
       if (lds(c, G) > budget[c.tier]) break;
+      const int64_t elem = prec == SHT_FP64 ? 8 : 4;
+      if (((int64_t)(G - 1) * npts + 2 * (int64_t)c.h) * elem >= ((int64_t)1 << 31)) break;
       gs = s + 1;
       best = rad;
     }
@@ -484,6 +488,15 @@ void fft_join(const sht_plan_t* plans, std::vector<FftItem>* tiers, std::vector<
   off[FFT_TIERS] = (int)out->size();
 }
 
+// The FFT sweeps address one ring's Fourier rows (both analysis slots, all
+// fields of the row) with 32-bit byte offsets.
+bool fourier_offsets_fit(const sht_plan_s* p) {
+  const int64_t csize = (p->prec == SHT_FP64) ? 16 : 8;
+  int mm = 0;
+  for (const RingInfo& r : p->rings) mm = std::max(mm, r.mmax);
+  return 2 * ((int64_t)mm + 1) * p->Fp * csize < ((int64_t)1 << 31);
+}
+
 int build_host(sht_plan_s* p) {
   const int N = p->N;
   // ---- geometry ----
@@ -517,6 +530,7 @@ int build_host(sht_plan_s* p) {
   }
   p->npts = p->ring_off[p->nlat];
   p->nfour = p->four_row[p->nlat];
+  if (!fourier_offsets_fit(p)) return SHT_EUNSUPPORTED;
 
   // ---- FFT classes (one per distinct half length) ----
   const int csize = (p->prec == SHT_FP64) ? 16 : 8;
@@ -553,7 +567,7 @@ int build_host(sht_plan_s* p) {
     p->classes.push_back(c);
   }
   p->fft_bytes = (size_t)off * csize;
-  choose_groups(p->prec, &p->classes);
+  choose_groups(p->prec, p->npts, &p->classes);
   for (auto& r : p->rings) {
     const int h = r.nlon / 2;
     r.cls = (int)(std::lower_bound(hs.begin(), hs.end(), h) - hs.begin());
@@ -1113,6 +1127,10 @@ int sht_plan_create_like(sht_plan_t* out, sht_plan_t base, int nfields, void* hi
   p->Fv = nfields;
   p->F = p->vec ? 2 * nfields : nfields;
   p->Fp = (int)round_up(p->F, FPAD);
+  if (!fourier_offsets_fit(p)) {
+    delete p;
+    return SHT_EUNSUPPORTED;
+  }
   p->dp = base->dp;
   p->dp.F = p->F;
   p->dp.Fp = p->Fp;

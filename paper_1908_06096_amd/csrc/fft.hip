@@ -98,6 +98,23 @@ __device__ __forceinline__ C buffer_load(__amdgpu_buffer_rsrc_t r, uint32_t byte
   if constexpr (sizeof(C) == 8) return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
   else return __builtin_bit_cast(C, __builtin_amdgcn_raw_buffer_load_b128(r, byte_off, 0, 0));
 }
+// The same over `bytes` bytes from a base that is the same on every lane:
+// loads past the range return zero and stores past it are dropped, which
+// the sweeps use in place of per-element guards (offsets stay below 2^31:
+// the host refuses plans whose ring blocks would not).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc_range(const void* base, uint32_t bytes) {
+  const uint64_t a = (uint64_t)base;
+  const uint64_t u = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(a >> 32)) << 32) |
+                     (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)a);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)u, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes), 0x00020000);
+}
+template <typename C>
+__device__ __forceinline__ void buffer_store(const C& v, __amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  if constexpr (sizeof(C) == 8)
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(gword2, v), r, byte_off, 0, 0);
+  else
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(gword4, v), r, byte_off, 0, 0);
+}
 
 // exp(-2 pi i j / R) at compile time: the angle is reduced exactly to
 // |r| <= pi/4 from the nearest quarter turn (4j - qR is an integer), then
@@ -639,7 +656,16 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
   const uint32_t fs = lds_stride(L);
   {
     // Z_q and Z_{h-q} are built from the same two coefficients X_q and
-    // X_{h-q}, so pair p = q (0 <= q <= h/2) loads them once and writes both
+    // X_{h-q}, so pair p = q (0 <= q <= h/2) loads them once and writes both.
+    // The loads go through descriptors: the group's Fourier rows 0..mmax of
+    // the ring (X_q = 0 above mmax, and X_h, read for q = 0, is past them as
+    // mmax < h), and the post and chirp tables (h entries each).  Fields past
+    // F read the row's padding columns; their transforms are never stored.
+    const __amdgpu_buffer_rsrc_t xr =
+        buffer_rsrc_range(fc + ri.frow * Fp + fb, (uint32_t)((mmax + 1) * Fp * (int64_t)sizeof(C)));
+    const __amdgpu_buffer_rsrc_t pr = buffer_rsrc_range(post, (uint32_t)(h * sizeof(C)));
+    const __amdgpu_buffer_rsrc_t cr = buffer_rsrc_range(chirp, blue ? (uint32_t)(h * sizeof(C)) : 0u);
+    const uint32_t rowb = (uint32_t)(Fp * sizeof(C));
     const int np = (h / 2 + 1) << gs;
     for (int e0 = threadIdx.x; e0 < np; e0 += FFT_SWEEP * NT) {
       // the factors of h - q follow from those of q: w^{-(h-q)} = -conj(w^{-q})
@@ -648,13 +674,16 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int e = e0 + u * NT;
-        const int s = e & (G - 1), q = e >> gs, q2 = h - q;
-        const bool ok = e < np && fb + s < fend;
-        const C* cf = fc + ri.frow * Fp + fb + s;
-        xa[u] = (ok && q <= mmax) ? gload(cf + q * Fp) : C{0, 0};
-        xb[u] = (ok && q >= 1 && q2 <= mmax) ? gload(cf + q2 * Fp) : C{0, 0};
-        pa[u] = ok ? gload(post + q) : C{1, 0};
-        ca[u] = (ok && blue) ? gload(chirp + q) : C{1, 0};
+        const uint32_t s = (uint32_t)(e & (G - 1)), q = (uint32_t)(e >> gs), q2 = (uint32_t)h - q;
+        xa[u] = xb[u] = pa[u] = ca[u] = C{0, 0};
+        // lanes past the pairs (most of a small ring's) skip the loads, whole
+        // waves at a time
+        if (e < np) {
+          xa[u] = buffer_load<C>(xr, q * rowb + s * (uint32_t)sizeof(C));
+          xb[u] = buffer_load<C>(xr, q2 * rowb + s * (uint32_t)sizeof(C));
+          pa[u] = buffer_load<C>(pr, q * (uint32_t)sizeof(C));
+          if (blue) ca[u] = buffer_load<C>(cr, q * (uint32_t)sizeof(C));
+        }
       }
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
@@ -738,16 +767,35 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   const int M = mmax + 1;
   const int f = fb + sub;
   const uint32_t dst = sub * fs;
+  // Grid loads through a descriptor from field fb's ring (the same on every
+  // lane) that ends after the h points of field fend - 1: fields past fend
+  // read zero; t >= h is selected to zero (other fields' rows follow).
+  // Chirp factors through one of h entries.  Fourier stores through a
+  // descriptor from field fb of the north ring's first row to the end of
+  // its rows 0..mmax (both slots): wavenumbers past mmax start past it and
+  // are dropped, and fields past F (zero transforms) write zeros into the
+  // rows' padding columns.
+  const __amdgpu_buffer_rsrc_t cr = buffer_rsrc_range(chirp, blue ? (uint32_t)(h * sizeof(C)) : 0u);
+  const uint32_t fo = (uint32_t)(f - fb) * (uint32_t)p.npts * (uint32_t)sizeof(T);
+  const uint32_t grange = (uint32_t)(((int64_t)(fend - 1 - fb) * p.npts + 2 * (int64_t)h) * (int64_t)sizeof(T));
+  const __amdgpu_buffer_rsrc_t orr = buffer_rsrc_range(
+      fc + (rn.frow * 2) * (int64_t)p.Fp + fb, (uint32_t)(2 * ((int64_t)mmax + 1) * p.Fp * (int64_t)sizeof(C)));
   for (int side = 0; side < 2; ++side) {
-    const C* g = (const C*)(grid + (int64_t)min(f, fend - 1) * p.npts + (side ? rs.goff : rn.goff));
+    const __amdgpu_buffer_rsrc_t gr =
+        buffer_rsrc_range(grid + (int64_t)fb * p.npts + (side ? rs.goff : rn.goff), grange);
     for (int t0 = lt; t0 < Q; t0 += FFT_SWEEP * nt) {
       C z[FFT_SWEEP], c[FFT_SWEEP];
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int t = t0 + u * nt;
-        const bool ok = t < h && f < fend;
-        z[u] = ok ? gload(g + t) : C{0, 0};
-        c[u] = (ok && blue) ? gload(chirp + t) : C{1, 0};
+        z[u] = C{0, 0};
+        c[u] = C{1, 0};
+        // the chirp-z padding (t >= h, more than half of those rings) loads
+        // nothing
+        if (t < h) {
+          z[u] = buffer_load<C>(gr, fo + (uint32_t)t * (uint32_t)sizeof(C));
+          if (blue) c[u] = buffer_load<C>(cr, (uint32_t)t * (uint32_t)sizeof(C));
+        }
       }
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
@@ -760,20 +808,25 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
     // chirp-z classes hold y_q: Z_m = c_m conj(y_m), and
     // conj Z_{h-m} = conj(c_{h-m}) y_{h-m} with c_{h-m} = (-1)^h c_m
     const int nm = M << gs;
+    const __amdgpu_buffer_rsrc_t pr = buffer_rsrc_range(post, (uint32_t)(h * sizeof(C)));
     for (int e0 = threadIdx.x; e0 < nm; e0 += FFT_SWEEP * NT) {
       C pm[FFT_SWEEP], cm[FFT_SWEEP];
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int e = e0 + u * NT;
-        pm[u] = e < nm ? gload(post + (e >> gs)) : C{0, 0};
-        cm[u] = (e < nm && blue) ? gload(chirp + (e >> gs)) : C{1, 0};
+        const uint32_t m = (uint32_t)(e >> gs);
+        pm[u] = C{0, 0};
+        cm[u] = C{1, 0};
+        if (e < nm) {
+          pm[u] = buffer_load<C>(pr, m * (uint32_t)sizeof(C));
+          if (blue) cm[u] = buffer_load<C>(cr, m * (uint32_t)sizeof(C));
+        }
       }
 #pragma unroll
       for (int u = 0; u < FFT_SWEEP; ++u) {
         const int e = e0 + u * NT;
         if (e >= nm) continue;
         const int s = e & (G - 1), m = e >> gs;
-        if (fb + s >= fend) continue;
         C zm = lds_load(lds_elem<C>(s * fs + m));
         C zr = lds_load(lds_elem<C>(s * fs + (m == 0 ? 0 : h - m)));
         if (blue) {
@@ -789,7 +842,8 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
         // X = sm/2 - (i/2) t
         C x = C{(T)0.5 * (sm.x + t.y), (T)0.5 * (sm.y - t.x)};
         if (m == 0) x = C{zm.x + zm.y, 0};
-        gstore(fc + ((rn.frow + m) * 2 + side) * (int64_t)p.Fp + fb + s, cscale(x, scale));
+        buffer_store(cscale(x, scale), orr,
+                     (((uint32_t)m * 2u + (uint32_t)side) * (uint32_t)p.Fp + (uint32_t)s) * (uint32_t)sizeof(C));
       }
     }
     // the next transform's input sweep overwrites this one
