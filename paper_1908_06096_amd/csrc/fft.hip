@@ -439,7 +439,8 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
         } else if constexpr (MODE == OUT_HEAD) {
           if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), y);
         } else if constexpr (MODE == OUT_GRID) {
-          if (io && o < h) gstore(io + o, cconj(y));
+          // plain transforms have L = h, so o < h always
+          if (io) gstore(io + o, cconj(y));
         } else {
           if (io && o < h) gstore(io + o, cmul(cconj(buffer_load<C>(ars, ao)), y));
         }
