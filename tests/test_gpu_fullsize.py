@@ -4,7 +4,10 @@ the benchmark times, on outputs the oracle computes one by one: sampled
 rings of the synthesis, sampled wavenumbers of the analysis, for fields at
 the start, middle and ragged end of the field range.  The inputs are 4
 distinct seeded fields repeated to 411 on the device (field f is field
-f mod 4), so the oracle only ever works on 4 fields."""
+f mod 4), so the oracle only ever works on 4 fields.  Every error is
+checked per field as well as over the sampled fields together; in FP32 and
+bf16x3 the synthesis of every ring of the sampled fields is also compared
+with the float64 form of the same coefficients on the GPU."""
 
 import numpy as np
 import pytest
@@ -89,21 +92,44 @@ def test_full_size_sampled(sht, case):
         rings = _rings(geo)
         _four, ref = oracle.inverse(spec_c, N, grid, rings=rings)
         got, want = [], []
+        per_field = []
         for fo in FIELDS:
-            for j in rings:
-                got.append(g[fo, geo["off"][j]:geo["off"][j + 1]].double().cpu().numpy())
-                want.append(ref[j][fo % D])
+            gf = [g[fo, geo["off"][j]:geo["off"][j + 1]].double().cpu().numpy() for j in rings]
+            wf = [ref[j][fo % D] for j in rings]
+            per_field.append(rel_l2(np.concatenate(gf), np.concatenate(wf)))
+            got += gf
+            want += wf
         err = rel_l2(np.concatenate(got), np.concatenate(want))
-        print(f"[{_ids(case)}] synthesis on rings {rings}: rel L2 {err:.3e}", flush=True)
+        print(f"[{_ids(case)}] synthesis on rings {rings}: rel L2 {err:.3e}, per field "
+              + ", ".join(f"{e:.3e}" for e in per_field), flush=True)
         assert err <= TOL[prec]
+        assert max(per_field) <= TOL[prec]
+
+        if prec != "fp64":
+            # every ring of the sampled fields against the float64 form of the
+            # same coefficients on the GPU (whose own rings are checked against
+            # the oracle in the fp64 case)
+            with sht.Plan(N, grid, D, "fp64") as p64:
+                g64 = p64.inverse(spec_t[:D].double())
+                torch.cuda.synchronize()
+                errs = [rel_l2(g[fo].double().cpu().numpy(), g64[fo % D].cpu().numpy()) for fo in FIELDS]
+                del g64
+            print(f"[{_ids(case)}] synthesis, all rings, against the fp64 form: per field "
+                  + ", ".join(f"{e:.3e}" for e in errs), flush=True)
+            assert max(errs) <= TOL[prec]
 
         # round trip of the same fields (band-limited input: exact up to rounding)
         back = plan.direct(g)
         torch.cuda.synchronize()
         b = back[FIELDS].double().cpu().numpy()
-        err = rel_l2(b[..., 0] + 1j * b[..., 1], spec_c[[fo % D for fo in FIELDS]])
-        print(f"[{_ids(case)}] round trip: rel L2 {err:.3e}", flush=True)
+        bc = b[..., 0] + 1j * b[..., 1]
+        sc = spec_c[[fo % D for fo in FIELDS]]
+        err = rel_l2(bc, sc)
+        per_field = [rel_l2(bc[i], sc[i]) for i in range(len(FIELDS))]
+        print(f"[{_ids(case)}] round trip: rel L2 {err:.3e}, per field "
+              + ", ".join(f"{e:.3e}" for e in per_field), flush=True)
         assert err <= TOL[prec]
+        assert max(per_field) <= TOL[prec]
         del g, back, spec_t
 
         # analysis of white noise on sampled wavenumbers
@@ -116,5 +142,8 @@ def test_full_size_sampled(sht, case):
         got = sh[..., 0] + 1j * sh[..., 1]
         want = ref[[fo % D for fo in FIELDS]][:, sel]
         err = rel_l2(got, want)
-        print(f"[{_ids(case)}] analysis on m {ms}: rel L2 {err:.3e}", flush=True)
+        per_field = [rel_l2(got[i], want[i]) for i in range(len(FIELDS))]
+        print(f"[{_ids(case)}] analysis on m {ms}: rel L2 {err:.3e}, per field "
+              + ", ".join(f"{e:.3e}" for e in per_field), flush=True)
         assert err <= TOL[prec]
+        assert max(per_field) <= TOL[prec]
