@@ -127,11 +127,16 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
   // FP32: spectral row k of parity p has its column index XORed with
   // 4 (2 p + (k / 2) mod 2).  The parities' planes and every other row share
   // banks, so the staging writes (lanes of two fields over 8 (parity, k)
-  // pairs) would meet on 4 bank groups; permuted they use all 16.  The
-  // permutation stays within 16-column blocks and is the same for a lane
-  // across the step's operand reads, which stay conflict-free.
-  constexpr bool BSWZ = sizeof(T) == 4;
-  auto bcol = [](int par, int k, int col) { return BSWZ ? col ^ (4 * (2 * par + ((k >> 1) & 1))) : col; };
+  // pairs) would meet on 4 bank groups; permuted they use all 16.  FP64:
+  // rows are 640 bytes apart, so the 16-byte stores of one field's 8 lanes
+  // (4 k x 2 parities, 16 bytes each) all met on one bank group; the column
+  // is XORed with 2 (2 (k mod 4) + p), which gives the 8 lanes 8 different
+  // 16-byte slots of 128 bytes.  Both permutations stay within 16-column
+  // blocks and are the same for a lane across the step's operand reads
+  // (k = 4 ks + lane / 16), which stay conflict-free.
+  auto bcol = [](int par, int k, int col) {
+    return sizeof(T) == 4 ? col ^ (4 * (2 * par + ((k >> 1) & 1))) : col ^ (2 * (2 * (k & 3) + par));
+  };
 
   const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
@@ -303,8 +308,13 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
   // four bank groups.  The operand reads (rings 4s + lane / 16) take a
   // permutation that is the same for a lane across the whole step and stays
   // within 16-column blocks, so they remain conflict-free.
-  constexpr bool TSWZ = sizeof(T) == 4;
-  auto tcol = [](int ring, int col) { return TSWZ ? col ^ (VN * ((ring >> 1) & 1)) : col; };
+  // FP64: rows are 640 bytes apart, so the 16-byte stores of 8 consecutive
+  // rings all met on one bank group; the 16-byte unit is XORed with the ring
+  // mod 8, which spreads them over 8 slots (the operand reads then take one
+  // of two permutations per lane, by ks mod 2).
+  auto tcol = [](int ring, int col) {
+    return sizeof(T) == 4 ? col ^ (VN * ((ring >> 1) & 1)) : col ^ (VN * (ring & 7));
+  };
 
   const MInfo mi = gload(p.ms + it.m);
   const int m = mi.m;
