@@ -140,9 +140,9 @@ enum sht_op {
 /* Column-tile variants of the Legendre products: the 2F real columns of a
  * product are cut into tiles of 128, 64 or 32 columns.  FP32 and FP64 plans
  * start with 32 columns when 2F <= 32, else 64 (FP64: 64 or 32 only).
- * BF16X3 plans start with C128 (synthesis tiles of 256 rings x 128 columns
- * on eight waves); C64 selects its 128 x 64 synthesis tiles; the analysis
- * tiles are 64 k x 128 columns in both. */
+ * BF16X3 plans start with C128 (MFMA 32x32x16: synthesis tiles of 128 rings
+ * x 128 columns, analysis tiles of 128 k x 128 columns); C64 selects tiles of
+ * 128 rings x 64 columns and 64 k x 128 columns (MFMA 16x16x32). */
 enum sht_tile { SHT_TILE_C128 = 0, SHT_TILE_C64 = 1, SHT_TILE_C32 = 2 };
 
 typedef struct sht_batch_s* sht_batch_t;

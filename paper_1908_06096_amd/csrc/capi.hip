@@ -165,7 +165,7 @@ int cu_count() {
 // sht_plan_set_tile and the batch autotuner can still choose them.
 int default_variant(int prec, int F) {
   const int cols = 2 * F;
-  if (prec == SHT_BF16X3) return TILE_C128;  // 256 x 128 synthesis tile: 6.8 against 9.6 ms at TCo1279 x 411
+  if (prec == SHT_BF16X3) return TILE_C128;  // wide tiles: 6.7 / 6.9 against 9.6 / 10.8 ms at TCo1279 x 411
   if (cols <= 32) return TILE_C32;
   return TILE_C64;
 }
@@ -315,7 +315,6 @@ void legendre_arrange(std::vector<WorkItem>* items, Steps steps) {
     for (int x = 0; x < NUM_XCD; ++x) items->push_back(r < q[x].size() ? q[x][r] : WorkItem{-1, 0, 0, 0});
 }
 
-// Arranged work lists of one plan.
 // Arranged work lists of one plan.  For a table-free plan the lists are the
 // chunks' lists back to back; inv_off / dir_off (if given) receive where
 // each chunk's items start (nchunks + 1 entries).

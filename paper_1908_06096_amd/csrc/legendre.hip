@@ -721,22 +721,23 @@ __device__ __forceinline__ void inverse_bf16x3_tile(const DevPlan& p, const Work
   __syncthreads();
 }
 
-// Synthesis in BF16 split precision on a wide tile: 256 rings x 128 real
-// columns, both parities, eight waves (512 threads, one work group per CU),
-// MFMA 32x32x16.  A step takes 16 k of each parity (32 consecutive n):
-// 32 KB of table and 16 KB of spectral operand move into LDS for 192 MFMAs,
-// twice the flops per byte of the 128 x 64 tile, and both stages are double
-// buffered (96 KB), so one barrier per step separates the copies of step
-// k + 1 from the products of step k.  Wave w owns rows 64 (w >> 1) and
-// columns 64 (w & 1) of both parities (2 x 2 blocks of 32 x 32 each), so
-// the N/S fold (S + A, S - A) happens in its registers.
+// Synthesis in BF16 split precision on a wide tile: 32 NW rings x 128 real
+// columns, both parities, NW waves, MFMA 32x32x16 (NW = 4: 128-ring tiles,
+// two work groups per CU; NW = 8: 256-ring tiles, one).  A step takes 16 k
+// of each parity (32 consecutive n): 4 NW KB of table and 16 KB of
+// spectral operand move into LDS for 24 NW MFMAs, and both
+// stages are double buffered (64 or 96 KB), so one barrier per step
+// separates the copies of step k + 1 from the products of step k.  Wave w
+// owns rows 64 (w >> 1) and columns 64 (w & 1) of both parities (2 x 2
+// blocks of 32 x 32 each), so the N/S fold (S + A, S - A) happens in its
+// registers.
 //
 // MFMA 32x32x16 bf16 operand placement, lane l: A[row l % 32][k 8 (l / 32)
 // + i], B[k 8 (l / 32) + i][col l % 32] (i < 8, one 16-byte operand);
 // accumulator element e holds D[8 (e / 4) + 4 (l / 32) + e % 4][l % 32].
 //
 // LDS stage layout, 16-byte units of 8 consecutive k:
-//   table     [parity][plane][k chunk (2)][row (256)]
+//   table     [parity][plane][k chunk (2)][row (32 NW)]
 //   spectral  [parity][plane][k chunk (2)][column (128) ^ chunk]
 // (the spectral column is XORed with the chunk so that the two chunks'
 // staging writes, which the lanes of one field make 4 bytes apart, fall on
@@ -749,11 +750,9 @@ __device__ inline f32x16 mfma32_bf16(const uint4& a, const uint4& b, f32x16 c) {
 }
 
 constexpr int BW_BN = 128, BW_KI = 16;
-// waves of the wide synthesis work group (rows = 32 per wave)
-#ifndef SHT_BW_WAVES
-#define SHT_BW_WAVES 4
-#endif
-constexpr int BW_WAVES = SHT_BW_WAVES;
+// waves of the wide synthesis work group: four (two work groups per CU)
+// measured 6.68 ms at TCo1279 x 411, eight (one per CU) 6.93 ms
+constexpr int BW_WAVES = 4;
 
 template <int NW>
 __device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const WorkItem it,
@@ -1473,8 +1472,8 @@ __global__ __launch_bounds__(512, 1) void legendre_direct_bf16x3_wide_kernel(con
 bool legendre_variant_supported(int prec, int variant) {
   if (prec == SHT_FP64) return variant == TILE_C64 || variant == TILE_C32;
   if (prec == SHT_FP32) return variant >= 0 && variant < NUM_TILE_VARIANTS;
-  // bf16x3: synthesis 128 x 64 (C64) or 256 x 128 (C128); analysis 64 k x 128
-  // columns (C64) or 128 k x 128 columns (C128)
+  // bf16x3: synthesis 128 x 64 (C64) or 128 x 128 (C128); analysis 64 k x
+  // 128 columns (C64) or 128 k x 128 columns (C128)
   return variant == TILE_C64 || variant == TILE_C128;
 }
 
