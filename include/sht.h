@@ -322,6 +322,9 @@ int sht_spectral_op(sht_plan_t plan, int op, int count, const void* in, void* ou
  * grid, the diffusion implicit in spectral space,
  *   g = synthesis(a);  g <- g + dt r g (1 - g);  b = analysis(g);
  *   a_n^m <- b_n^m / (1 + dt nu n (n + 1)).
+ * The grid-point step is applied as the synthesis stores the grid, and the
+ * diffusion as the analysis stores the coefficients (each value rounded
+ * once after the transform's own rounding): a step is the four stages.
  * A stepper binds a scalar plan to the state `spec` ([F][nspec], updated in
  * place every step), a grid and a workspace (scratch).  With SHT_STEP_GRAPH
  * `graph_steps` consecutive steps are captured once into a HIP graph on

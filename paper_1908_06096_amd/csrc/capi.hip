@@ -1360,9 +1360,13 @@ int stage_legendre_inverse(sht_plan_t p, const void* spec, void* four, void* str
   return SHT_OK;
 }
 
-int stage_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream) {
-  HIP_TRY(fft_launch_tiers(true, p->d_self, p->prec, p->d_syn, p->syn_off, nullptr,
-                           bind_of(nullptr, grid, four), p->lds_syn_t, (hipStream_t)stream));
+// grid_a != 0: each grid value g is stored as g + grid_a g (1 - g) (the
+// grid-point step of a time step, fused into the last pass's stores)
+int stage_fourier_synthesis(sht_plan_t p, const void* four, void* grid, void* stream, double grid_a = 0.0) {
+  IoBind io = bind_of(nullptr, grid, four);
+  io.grid_a = grid_a;
+  HIP_TRY(fft_launch_tiers(true, p->d_self, p->prec, p->d_syn, p->syn_off, nullptr, io, p->lds_syn_t,
+                           (hipStream_t)stream));
   return SHT_OK;
 }
 
@@ -1372,12 +1376,15 @@ int stage_fourier_analysis(sht_plan_t p, const void* grid, void* four, void* str
   return SHT_OK;
 }
 
-int stage_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream) {
+// spec_c != 0: each coefficient is stored divided by 1 + spec_c n (n + 1)
+// (the implicit diffusion of a time step, fused into the products' stores)
+int stage_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stream, double spec_c = 0.0) {
   const hipStream_t s = (hipStream_t)stream;
   if (p->notab) {
     void* tab = chunk_tables(p, const_cast<void*>(four));
     IoBind io = bind_of(spec, nullptr, four);
     io.pad = tab;
+    io.spec_c = spec_c;
     for (size_t c = 0; c + 1 < p->chunk_m.size(); ++c) {
       HIP_TRY(make_chunk_tables(p, (int)c, tab, s));
       const int n = p->dir_off[c + 1] - p->dir_off[c];
@@ -1385,8 +1392,10 @@ int stage_legendre_direct(sht_plan_t p, const void* four, void* spec, void* stre
     }
     return SHT_OK;
   }
-  HIP_TRY(launch_legendre_direct(p->d_self, p->prec, p->variant, p->d_dir, (int)p->dir_items.size(), nullptr,
-                                 bind_of(spec, nullptr, four), (int)p->dir_items.size(), s));
+  IoBind io = bind_of(spec, nullptr, four);
+  io.spec_c = spec_c;
+  HIP_TRY(launch_legendre_direct(p->d_self, p->prec, p->variant, p->d_dir, (int)p->dir_items.size(), nullptr, io,
+                                 (int)p->dir_items.size(), s));
   return SHT_OK;
 }
 
@@ -1661,19 +1670,22 @@ struct sht_stepper_s {
 
 namespace {
 
-// One time step on the stepper's buffers: synthesis, the logistic term on
-// the grid, analysis, implicit diffusion.
+// One time step on the stepper's buffers, for the reaction-diffusion
+// equation du/dt = nu Lap u + r u (1 - u) on the unit sphere (report
+// sections 4.2.2-4.2.3: the loop over time steps of synthesis, grid-point
+// computations and analysis, on arrays allocated outside it): semi-implicit
+// Euler, the logistic term explicit on the grid, g <- g + dt r g (1 - g),
+// fused into the synthesis' grid stores, and the diffusion implicit in
+// spectral space (Lap -> -n (n + 1)), a_n^m <- a_n^m / (1 + dt nu n (n + 1)),
+// fused into the analysis' coefficient stores: four stages, no pass of its
+// own over the grid or the coefficients.
 int enqueue_step(const sht_stepper_s* st, hipStream_t s) {
   sht_plan_t p = st->plan;
   int rc = stage_legendre_inverse(p, st->spec, st->ws, s);
-  if (rc == SHT_OK) rc = stage_fourier_synthesis(p, st->ws, st->grid, s);
-  if (rc != SHT_OK) return rc;
-  HIP_TRY(launch_logistic(p->prec, (int64_t)p->F * p->npts, st->dt * st->rate, st->grid, s));
-  rc = stage_fourier_analysis(p, st->grid, st->ws, s);
-  if (rc == SHT_OK) rc = stage_legendre_direct(p, st->ws, st->spec, s);
-  if (rc != SHT_OK) return rc;
-  HIP_TRY(launch_implicit_diffusion(p->prec, p->N, p->F, st->dt * st->nu, st->spec, s));
-  return SHT_OK;
+  if (rc == SHT_OK) rc = stage_fourier_synthesis(p, st->ws, st->grid, s, st->dt * st->rate);
+  if (rc == SHT_OK) rc = stage_fourier_analysis(p, st->grid, st->ws, s);
+  if (rc == SHT_OK) rc = stage_legendre_direct(p, st->ws, st->spec, s, st->dt * st->nu);
+  return rc;
 }
 
 // Capture graph_steps steps into one graph on stream `s` (which must not be

@@ -372,7 +372,7 @@ __device__ inline void butterfly(typename V2T<T>::type* v) {
 }
 
 // What the last pass of a transform does with its outputs.
-enum PassOut { OUT_PLAIN = 0, OUT_HEAD = 1, OUT_GRID = 2, OUT_GRID_CHIRP = 3 };
+enum PassOut { OUT_PLAIN = 0, OUT_HEAD = 1, OUT_GRID = 2, OUT_GRID_CHIRP = 3, OUT_GRID_LOG = 4, OUT_GRID_CHIRP_LOG = 5 };
 
 // One Stockham pass of radix R over L points in LDS, after Ns points have
 // been combined, carried out by the nt threads (thread lt) that own this
@@ -386,14 +386,17 @@ enum PassOut { OUT_PLAIN = 0, OUT_HEAD = 1, OUT_GRID = 2, OUT_GRID_CHIRP = 3 };
 //     reads afterwards);
 //   OUT_GRID writes conj(y_q) and OUT_GRID_CHIRP writes conj(c_q) y_q, the
 //     conjugates of y_q and of c_q conj(y_q), for q < h to io in device
-//     memory (nothing when io is null).
+//     memory (nothing when io is null); OUT_GRID_LOG and OUT_GRID_CHIRP_LOG
+//     write each real value g of those as g + ga g (1 - g) (the grid-point
+//     step of a time step), in instantiations of their own so that the plain
+//     transforms' stores carry no test of ga.
 // Each instantiation is its own non-inlined function so that its registers
 // are allocated for it alone.  Every thread of the work group calls it (the
 // barriers).
 template <typename T, int R, int MODE>
 __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
-                                           typename V2T<T>::type* io, int h, int lt, int nt) {
+                                           typename V2T<T>::type* io, int h, int lt, int nt, T ga) {
   typedef typename V2T<T>::type C;
   // a radix above FFT_REGS (a prime) runs as the first pass only (the plan
   // sees to it): Ns = 1, no twiddles, one butterfly per thread
@@ -438,11 +441,19 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
           lds_store(lds_elem<C>(e0 + (uint32_t)o), y);
         } else if constexpr (MODE == OUT_HEAD) {
           if (o < h) lds_store(lds_elem<C>(e0 + (uint32_t)o), y);
-        } else if constexpr (MODE == OUT_GRID) {
+        } else if constexpr (MODE == OUT_GRID || MODE == OUT_GRID_LOG) {
           // plain transforms have L = h, so o < h always
-          if (io) gstore(io + o, cconj(y));
+          if (io) {
+            C g = cconj(y);
+            if constexpr (MODE == OUT_GRID_LOG) g = C{logistic_step(g.x, ga), logistic_step(g.y, ga)};
+            gstore(io + o, g);
+          }
         } else {
-          if (io && o < h) gstore(io + o, cmul(cconj(buffer_load<C>(ars, ao)), y));
+          if (io && o < h) {
+            C g = cmul(cconj(buffer_load<C>(ars, ao)), y);
+            if constexpr (MODE == OUT_GRID_CHIRP_LOG) g = C{logistic_step(g.x, ga), logistic_step(g.y, ga)};
+            gstore(io + o, g);
+          }
         }
       };
       if constexpr (odd_prime_radix(R)) {
@@ -460,12 +471,13 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
 template <typename T, int MODE, bool BIG>
 __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
                                      const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
-                                     typename V2T<T>::type* io, int h, int lt, int nt) {
-#define SHT_PASS(RR) stockham_pass<T, RR, MODE>(e0, L, Ns, tw, aux, io, h, lt, nt)
+                                     typename V2T<T>::type* io, int h, int lt, int nt, T ga = T(0)) {
+#define SHT_PASS(RR) stockham_pass<T, RR, MODE>(e0, L, Ns, tw, aux, io, h, lt, nt, ga)
   // radices with a factor above 5 occur only in plain transforms of length h
   // (the chirp-z lengths are 5-smooth); the primes above FFT_BIG_PRIME only
   // in the BIG kernels, and only in FP32
-  if constexpr ((MODE == OUT_PLAIN || MODE == OUT_GRID) && BIG && sizeof(T) == 4) {
+  constexpr bool PLAIN_LEN = MODE == OUT_PLAIN || MODE == OUT_GRID || MODE == OUT_GRID_LOG;
+  if constexpr (PLAIN_LEN && BIG && sizeof(T) == 4) {
     switch (R) {
       case 47: SHT_PASS(47); return;
       case 43: SHT_PASS(43); return;
@@ -476,7 +488,7 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
       default: break;
     }
   }
-  if constexpr (MODE == OUT_PLAIN || MODE == OUT_GRID) {
+  if constexpr (PLAIN_LEN) {
     switch (R) {
       case 23: SHT_PASS(23); return;
       case 19: SHT_PASS(19); return;
@@ -513,10 +525,10 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
 template <typename T, int MODE, bool BIG>
 __device__ __forceinline__ void fft_passes(uint32_t e0, int L, const int32_t* rad, int q0, int q1, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
-                                           typename V2T<T>::type* io, int h, int lt, int nt) {
+                                           typename V2T<T>::type* io, int h, int lt, int nt, T ga = T(0)) {
   for (int q = q0; q < q1; ++q) {
     const int R = gload(rad + q);
-    if (q == q1 - 1) pass_dispatch<T, MODE, BIG>(R, e0, L, Ns, tw, aux, io, h, lt, nt);
+    if (q == q1 - 1) pass_dispatch<T, MODE, BIG>(R, e0, L, Ns, tw, aux, io, h, lt, nt, ga);
     else pass_dispatch<T, OUT_PLAIN, BIG>(R, e0, L, Ns, tw, nullptr, nullptr, h, lt, nt);
     tw += Ns * (R - 1);
     Ns *= R;
@@ -603,20 +615,22 @@ __device__ __forceinline__ void middle_dispatch(int R, uint32_t e0, int L, const
 // same radix, so the second DFT's first pass fuses with the first DFT's
 // last (a chirp-z length exceeds the largest radix, so each DFT has at
 // least two passes).
-template <typename T, bool GRID_OUT, bool BIG>
+template <typename T, bool GRID_OUT, bool BIG, bool LOG = false>
 __device__ __forceinline__ void dft_h(uint32_t e0, const FftClass& c, const int32_t* rad,
-                      const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt) {
+                      const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt, T ga = T(0)) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
   const int p = c.nrad;
+  constexpr int GRID_MODE = LOG ? OUT_GRID_LOG : OUT_GRID;
+  constexpr int CHIRP_MODE = LOG ? OUT_GRID_CHIRP_LOG : OUT_GRID_CHIRP;
   if (!c.bluestein) {
-    fft_passes<T, GRID_OUT ? OUT_GRID : OUT_PLAIN, BIG>(e0, c.L, rad, 0, p, 1, tw, nullptr, io, c.h, lt, nt);
+    fft_passes<T, GRID_OUT ? GRID_MODE : OUT_PLAIN, BIG>(e0, c.L, rad, 0, p, 1, tw, nullptr, io, c.h, lt, nt, ga);
     return;
   }
   const int R = gload(rad);
   fft_passes<T, OUT_PLAIN, false>(e0, c.L, rad, 0, p - 1, 1, tw, nullptr, nullptr, c.h, lt, nt);
   middle_dispatch<T>(R, e0, c.L, tw + (c.L / R - 1), tabs + c.khat_off, lt, nt);
-  fft_passes<T, GRID_OUT ? OUT_GRID_CHIRP : OUT_HEAD, false>(e0, c.L, rad, 1, p, R, tw + (R - 1),
-                                                             tabs + c.chirp_off, io, c.h, lt, nt);
+  fft_passes<T, GRID_OUT ? CHIRP_MODE : OUT_HEAD, false>(e0, c.L, rad, 1, p, R, tw + (R - 1), tabs + c.chirp_off,
+                                                         io, c.h, lt, nt, ga);
 }
 
 // Sweeps over a ring (gathers, scatters) issue the global loads of
@@ -639,7 +653,7 @@ size_t fft_grid_blocks(int nitems) { return (size_t)nitems; }
 
 template <typename T, int NT, bool BIG>
 __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int fb, int fend,
-                                                const T* __restrict__ four, T* __restrict__ grid) {
+                                                const T* __restrict__ four, T* __restrict__ grid, T ga) {
   typedef typename V2T<T>::type C;
   const RingInfo ri = gload(p.rings + ring);
   const FftClass cl = gload(p.classes + ri.cls);
@@ -728,7 +742,10 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
     const int f = fb + sub;
     C* g = f < fend ? (C*)(grid + (int64_t)f * p.npts + ri.goff) : nullptr;
     // the last pass writes the grid (the conjugate of the inverse transform)
-    dft_h<T, true, BIG>(sub * fs, cl, rad, tabs, g, lt, nt);
+    // the time step's grid-point operation has stores of its own (the
+    // choice is uniform across the work group)
+    if (ga != T(0)) dft_h<T, true, BIG, true>(sub * fs, cl, rad, tabs, g, lt, nt, ga);
+    else dft_h<T, true, BIG>(sub * fs, cl, rad, tabs, g, lt, nt);
   }
 }
 
@@ -877,7 +894,7 @@ __global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_synthesis_kern
     if (it.ring < 0) continue;
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    synthesis_group<T, NT, BIG>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid);
+    synthesis_group<T, NT, BIG>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid, (T)b.grid_a);
   }
 }
 

@@ -284,7 +284,7 @@ __device__ __forceinline__ void inverse_tile(const DevPlan& p, const WorkItem it
 
 template <typename T, int BC, int BK, int KJ, int WKW>
 __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it, const T* __restrict__ four,
-                                            T* __restrict__ spec) {
+                                            T* __restrict__ spec, double sc) {
   typedef typename Acc<T>::type acc_t;
   typedef typename Vec<T>::type V;
   typedef typename Vec<T>::pair C2;
@@ -440,6 +440,8 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
       const int k = it.t0 + wc * WK + j * 16 + (lane & 15);
       if (k >= K) continue;
       C2* dst = (C2*)spec + (mi.spec_off + 2 * k + par);
+      // fused implicit diffusion of a time step (sc != 0)
+      const T fd = sc != 0.0 ? diffusion_factor<T>(m + 2 * k + par, sc) : T(1);
 #pragma unroll
       for (int i = 0; i < IC; ++i) {
         if constexpr (sizeof(T) == 4) {
@@ -450,6 +452,7 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
             if (c < twoF) {
               C2 v = C2{acc[par][i][j][e], acc[par][i][j][e + 1]};
               if (m == 0) v.y = 0;
+              if (sc != 0.0) v = C2{v.x * fd, v.y * fd};
               gstore(dst + (int64_t)(c >> 1) * p.nspec, v);
             }
           }
@@ -460,6 +463,7 @@ __device__ __forceinline__ void direct_tile(const DevPlan& p, const WorkItem it,
             if (c < twoF) {
               T v = acc[par][i][j][e];
               if (m == 0 && (c & 1)) v = 0;
+              if (sc != 0.0) v *= fd;
               gstore((T*)(dst + (int64_t)(c >> 1) * p.nspec) + (c & 1), v);
             }
           }
@@ -944,7 +948,8 @@ __device__ __forceinline__ void inverse_bf16x3_wide_tile(const DevPlan& p, const
 // looked up a step ahead of the rows' loads.
 template <int BC, int BK>
 __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkItem it,
-                                                   const float* __restrict__ four, float* __restrict__ spec) {
+                                                   const float* __restrict__ four, float* __restrict__ spec,
+                                                   double sc) {
   const int64_t plane = p.tab_plane;
   constexpr int KJ = 32;
   constexpr int WC = BC / 2, WK = BK / 2;
@@ -1111,6 +1116,7 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
       const int k = it.t0 + wc * WK + j * 16 + (lane & 15);
       if (k >= K) continue;
       float2* dst = (float2*)spec + (mi.spec_off + 2 * k + par);
+      const float fd = sc != 0.0 ? diffusion_factor<float>(m + 2 * k + par, sc) : 1.f;
 #pragma unroll
       for (int i = 0; i < IC; ++i) {
 #pragma unroll
@@ -1119,6 +1125,7 @@ __device__ __forceinline__ void direct_bf16x3_tile(const DevPlan& p, const WorkI
           if (c < twoF) {
             float2 v = make_float2(acc[par][i][j][e], acc[par][i][j][e + 1]);
             if (m == 0) v.y = 0.f;
+            if (sc != 0.0) v = make_float2(v.x * fd, v.y * fd);
             gstore(dst + (int64_t)(c >> 1) * p.nspec, v);
           }
         }
@@ -1160,7 +1167,8 @@ __device__ __forceinline__ uint2 lds_read_tr16(const SHT_LDS void* a) {
 }
 
 __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const WorkItem it,
-                                                        const float* __restrict__ four, float* __restrict__ spec) {
+                                                        const float* __restrict__ four, float* __restrict__ spec,
+                                                        double sc) {
   constexpr int BK = DW_BK, BC = DW_BC, KJ = DW_KJ, XROW = DW_XROW;
   constexpr int NCH = BK / KCH;                 // table chunks per parity (16)
   constexpr int TS = 2 * 2 * NCH * KJ;          // 16-byte units of a table stage
@@ -1347,6 +1355,7 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
     const int k = it.t0 + 64 * kh + 32 * j + (lane & 31);
     if (k >= K) continue;
     float2* dst = (float2*)spec + (mi.spec_off + 2 * k + par);
+    const float fd = sc != 0.0 ? diffusion_factor<float>(m + 2 * k + par, sc) : 1.f;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
 #pragma unroll
@@ -1355,6 +1364,7 @@ __device__ __forceinline__ void direct_bf16x3_wide_tile(const DevPlan& p, const 
         if (c < twoF) {
           float2 v = make_float2(acc[i][j][e], acc[i][j][e + 1]);
           if (m == 0) v.y = 0.f;
+          if (sc != 0.0) v = make_float2(v.x * fd, v.y * fd);
           gstore(dst + (int64_t)(c >> 1) * p.nspec, v);
         }
       }
@@ -1391,7 +1401,7 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_kernel(const DevPlan* 
     DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
-    direct_tile<T, BC, BK, KJ, WKW>(p, it, (const T*)b.ws, (T*)b.spec);
+    direct_tile<T, BC, BK, KJ, WKW>(p, it, (const T*)b.ws, (T*)b.spec, b.spec_c);
   }
 }
 
@@ -1431,7 +1441,7 @@ __global__ __launch_bounds__(256, 2) void legendre_direct_bf16x3_kernel(const De
     DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
-    direct_bf16x3_tile<BC, BK>(p, it, (const float*)b.ws, (float*)b.spec);
+    direct_bf16x3_tile<BC, BK>(p, it, (const float*)b.ws, (float*)b.spec, b.spec_c);
   }
 }
 
@@ -1445,7 +1455,7 @@ __global__ __launch_bounds__(512, 1) void legendre_direct_bf16x3_wide_kernel(con
     DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
     if (b.pad) p.tab = b.pad;  // tables made for this call (table-free plans)
-    direct_bf16x3_wide_tile(p, it, (const float*)b.ws, (float*)b.spec);
+    direct_bf16x3_wide_tile(p, it, (const float*)b.ws, (float*)b.spec, b.spec_c);
   }
 }
 

@@ -187,7 +187,21 @@ struct IoBind {
   void* grid;
   void* ws;
   void* pad;  // Legendre tables to use instead of the plan's (table-free plans), or null
+  // pointwise steps fused into the stores of a time step (0: none):
+  double grid_a;  // synthesis grid values g <- g + a g (1 - g)
+  double spec_c;  // analysis coefficients a_n^m <- a_n^m / (1 + c n (n + 1))
 };
+
+// The two pointwise steps of the reaction-diffusion time step, with one
+// rounding order wherever they are applied.
+template <typename T>
+__device__ __forceinline__ T logistic_step(T g, T a) {
+  return __builtin_fma(a * g, T(1) - g, g);
+}
+template <typename T>
+__device__ __forceinline__ T diffusion_factor(int n, double c) {
+  return (T)(1.0 / (1.0 + c * (double)n * (double)(n + 1)));
+}
 
 // Column-tile variants of the Legendre products (2F real columns per m):
 // 128, 64 or 32 columns per tile.  Narrow tiles keep small field counts
@@ -257,8 +271,6 @@ hipError_t launch_spectral_op(int N, int count, int op, int prec, const void* in
 hipError_t launch_analysis_weight(int nlat, const double* mu, const double* w, double* wa, hipStream_t s);
 
 // stepper.hip: the grid-point and spectral operations of the time step.
-hipError_t launch_logistic(int prec, int64_t n, double a, void* grid, hipStream_t s);
-hipError_t launch_implicit_diffusion(int prec, int N, int F, double c, void* spec, hipStream_t s);
 
 // fft.hip.  Same launch model, one launch per tier: the items of one launch
 // all belong to classes of that tier.
