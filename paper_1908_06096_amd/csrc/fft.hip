@@ -757,9 +757,13 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
 //   row: slot 0 for the ring, slot 1 for its mirror (the Legendre analysis
 //   forms S = N + S' and A = N - S' as it stages them, so neither ring
 //   waits in LDS for the other; one work item still takes both, which
-//   measured faster than one ring per item).  The output step writes
-//   element e as (m = e / G, s = e mod G) so that neighbouring lanes write
-//   neighbouring fields of one Fourier row.
+//   measured faster than one ring per item).  An item of at most G/2 fields
+//   (the few fields of a small transform) transforms both rings at once:
+//   the mirror's fields take the upper half of the G field slots.  The
+//   halves meet at thread NT/2, a wave boundary, so every wave's ring is
+//   uniform.  Otherwise the rings go one after the other.  The output step
+//   writes element e as (m = e / G, slot s = e mod G) so that neighbouring
+//   lanes write neighbouring fields of one Fourier row.
 // ---------------------------------------------------------------------------
 
 template <typename T, int NT, bool BIG>
@@ -783,7 +787,10 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   const int sub = threadIdx.x / nt, lt = threadIdx.x - sub * nt;
   const int Q = blue ? L : h;
   const int M = mmax + 1;
-  const int f = fb + sub;
+  const int half = G >> 1;
+  const bool both = fend - fb <= half;
+  const int my_side = both && sub >= half ? 1 : 0;
+  const int f = fb + sub - my_side * half;
   const uint32_t dst = sub * fs;
   // Grid loads through a descriptor from field fb's ring (the same on every
   // lane) that ends after the h points of field fend - 1: fields past fend
@@ -798,7 +805,8 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
   const uint32_t grange = (uint32_t)(((int64_t)(fend - 1 - fb) * p.npts + 2 * (int64_t)h) * (int64_t)sizeof(T));
   const __amdgpu_buffer_rsrc_t orr = buffer_rsrc_range(
       fc + (rn.frow * 2) * (int64_t)p.Fp + fb, (uint32_t)(2 * ((int64_t)mmax + 1) * p.Fp * (int64_t)sizeof(C)));
-  for (int side = 0; side < 2; ++side) {
+  for (int pass = 0; pass < (both ? 1 : 2); ++pass) {
+    const int side = both ? my_side : pass;
     const __amdgpu_buffer_rsrc_t gr =
         buffer_rsrc_range(grid + (int64_t)fb * p.npts + (side ? rs.goff : rn.goff), grange);
     for (int t0 = lt; t0 < Q; t0 += FFT_SWEEP * nt) {
@@ -845,6 +853,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
         const int e = e0 + u * NT;
         if (e >= nm) continue;
         const int s = e & (G - 1), m = e >> gs;
+        const int es = both ? (s >= half ? 1 : 0) : side;  // the ring of slot s
         C zm = lds_load(lds_elem<C>(s * fs + m));
         C zr = lds_load(lds_elem<C>(s * fs + (m == 0 ? 0 : h - m)));
         if (blue) {
@@ -861,7 +870,8 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
         C x = C{(T)0.5 * (sm.x + t.y), (T)0.5 * (sm.y - t.x)};
         if (m == 0) x = C{zm.x + zm.y, 0};
         buffer_store(cscale(x, scale), orr,
-                     (((uint32_t)m * 2u + (uint32_t)side) * (uint32_t)p.Fp + (uint32_t)s) * (uint32_t)sizeof(C));
+                     (((uint32_t)m * 2u + (uint32_t)es) * (uint32_t)p.Fp + (uint32_t)(s - es * half * both)) *
+                         (uint32_t)sizeof(C));
       }
     }
     // the next transform's input sweep overwrites this one
