@@ -360,8 +360,8 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
     for (int f0 = 0; f0 < p->F; f0 += FFT_FCHUNK) {
       const int fend = std::min(f0 + FFT_FCHUNK, p->F);
       const int t = p->classes[p->rings[j].cls].tier;
-      syn[t].push_back(FftItem{j, f0, plan, fend});
-      if (j < p->nh) ana[t].push_back(FftItem{j, f0, plan, fend});
+      syn[t].push_back(FftItem{j, f0, plan, fend, p->rings[j].cls});
+      if (j < p->nh) ana[t].push_back(FftItem{j, f0, plan, fend, p->rings[j].cls});
     }
 }
 
@@ -391,9 +391,9 @@ void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
         if (k < nc && j < ng[k]) {
           const FftItem& c = chunks[c0 + k];
           const int f0 = c.f0 + j * G[k];
-          items->push_back(FftItem{c.ring, f0, c.plan, std::min(f0 + G[k], c.fend)});
+          items->push_back(FftItem{c.ring, f0, c.plan, std::min(f0 + G[k], c.fend), c.cls});
         } else {
-          items->push_back(FftItem{-1, 0, 0, 0});
+          items->push_back(FftItem{-1, 0, 0, 0, 0});
         }
       }
   }
@@ -567,6 +567,11 @@ int build_host(sht_plan_s* p) {
   }
   p->fft_bytes = (size_t)off * csize;
   choose_groups(p->prec, p->npts, &p->classes);
+  for (FftClass& c : p->classes) {
+    if (c.nrad > FFT_PACK_RADICES) return SHT_EUNSUPPORTED;
+    c.radpack = 0;
+    for (int q = 0; q < c.nrad; ++q) c.radpack |= (uint64_t)c.rad[q] << (6 * q);
+  }
   for (auto& r : p->rings) {
     const int h = r.nlon / 2;
     r.cls = (int)(std::lower_bound(hs.begin(), hs.end(), h) - hs.begin());

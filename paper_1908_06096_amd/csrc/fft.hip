@@ -518,16 +518,16 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
 #undef SHT_PASS
 }
 
-// Passes q0 <= q < q1 of a forward DFT of L points held in LDS, starting
-// after Ns points have been combined with tw at pass q0's table; the last of
-// them applies MODE with aux and io.  All passes from Ns = 1: natural order
-// in and out.
+// Passes q0 <= q < q1 of a forward DFT of L points held in LDS (radices
+// packed in rp), starting after Ns points have been combined with tw at pass
+// q0's table; the last of them applies MODE with aux and io.  All passes
+// from Ns = 1: natural order in and out.
 template <typename T, int MODE, bool BIG>
-__device__ __forceinline__ void fft_passes(uint32_t e0, int L, const int32_t* rad, int q0, int q1, int Ns,
+__device__ __forceinline__ void fft_passes(uint32_t e0, int L, uint64_t rp, int q0, int q1, int Ns,
                                            const typename V2T<T>::type* tw, const typename V2T<T>::type* aux,
                                            typename V2T<T>::type* io, int h, int lt, int nt, T ga = T(0)) {
   for (int q = q0; q < q1; ++q) {
-    const int R = gload(rad + q);
+    const int R = packed_radix(rp, q);
     if (q == q1 - 1) pass_dispatch<T, MODE, BIG>(R, e0, L, Ns, tw, aux, io, h, lt, nt, ga);
     else pass_dispatch<T, OUT_PLAIN, BIG>(R, e0, L, Ns, tw, nullptr, nullptr, h, lt, nt);
     tw += Ns * (R - 1);
@@ -616,20 +616,25 @@ __device__ __forceinline__ void middle_dispatch(int R, uint32_t e0, int L, const
 // last (a chirp-z length exceeds the largest radix, so each DFT has at
 // least two passes).
 template <typename T, bool GRID_OUT, bool BIG, bool LOG = false>
-__device__ __forceinline__ void dft_h(uint32_t e0, const FftClass& c, const int32_t* rad,
+__device__ __forceinline__ void dft_h(uint32_t e0, const FftClass& c,
                       const typename V2T<T>::type* tabs, typename V2T<T>::type* io, int lt, int nt, T ga = T(0)) {
   const typename V2T<T>::type* tw = tabs + c.root_off;
   const int p = c.nrad;
+  // the packed radices are the same on every lane: in scalar registers they
+  // stay out of the vector registers the code around the pass calls holds
+  // (as a vector value the analysis kernel spilled, 2 ms slower at TCo1279)
+  const uint64_t rp = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(c.radpack >> 32)) << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)c.radpack);
   constexpr int GRID_MODE = LOG ? OUT_GRID_LOG : OUT_GRID;
   constexpr int CHIRP_MODE = LOG ? OUT_GRID_CHIRP_LOG : OUT_GRID_CHIRP;
   if (!c.bluestein) {
-    fft_passes<T, GRID_OUT ? GRID_MODE : OUT_PLAIN, BIG>(e0, c.L, rad, 0, p, 1, tw, nullptr, io, c.h, lt, nt, ga);
+    fft_passes<T, GRID_OUT ? GRID_MODE : OUT_PLAIN, BIG>(e0, c.L, rp, 0, p, 1, tw, nullptr, io, c.h, lt, nt, ga);
     return;
   }
-  const int R = gload(rad);
-  fft_passes<T, OUT_PLAIN, false>(e0, c.L, rad, 0, p - 1, 1, tw, nullptr, nullptr, c.h, lt, nt);
+  const int R = packed_radix(rp, 0);
+  fft_passes<T, OUT_PLAIN, false>(e0, c.L, rp, 0, p - 1, 1, tw, nullptr, nullptr, c.h, lt, nt);
   middle_dispatch<T>(R, e0, c.L, tw + (c.L / R - 1), tabs + c.khat_off, lt, nt);
-  fft_passes<T, GRID_OUT ? CHIRP_MODE : OUT_HEAD, false>(e0, c.L, rad, 1, p, R, tw + (R - 1), tabs + c.chirp_off,
+  fft_passes<T, GRID_OUT ? CHIRP_MODE : OUT_HEAD, false>(e0, c.L, rp, 1, p, R, tw + (R - 1), tabs + c.chirp_off,
                                                          io, c.h, lt, nt, ga);
 }
 
@@ -652,12 +657,11 @@ size_t fft_grid_blocks(int nitems) { return (size_t)nitems; }
 // ---------------------------------------------------------------------------
 
 template <typename T, int NT, bool BIG>
-__device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int fb, int fend,
+__device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int cls, int fb, int fend,
                                                 const T* __restrict__ four, T* __restrict__ grid, T ga) {
   typedef typename V2T<T>::type C;
   const RingInfo ri = gload(p.rings + ring);
-  const FftClass cl = gload(p.classes + ri.cls);
-  const int32_t* rad = p.classes[ri.cls].rad;
+  const FftClass cl = gload(p.classes + cls);
   const C* tabs = (const C*)p.fft;
   const C* post = tabs + cl.post_off;
   const C* chirp = tabs + cl.chirp_off;
@@ -744,8 +748,8 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
     // the last pass writes the grid (the conjugate of the inverse transform)
     // the time step's grid-point operation has stores of its own (the
     // choice is uniform across the work group)
-    if (ga != T(0)) dft_h<T, true, BIG, true>(sub * fs, cl, rad, tabs, g, lt, nt, ga);
-    else dft_h<T, true, BIG>(sub * fs, cl, rad, tabs, g, lt, nt);
+    if (ga != T(0)) dft_h<T, true, BIG, true>(sub * fs, cl, tabs, g, lt, nt, ga);
+    else dft_h<T, true, BIG>(sub * fs, cl, tabs, g, lt, nt);
   }
 }
 
@@ -767,13 +771,13 @@ __device__ __forceinline__ void synthesis_group(const DevPlan& p, int ring, int 
 // ---------------------------------------------------------------------------
 
 template <typename T, int NT, bool BIG>
-__device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int fb, int fend,
+__device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int cls, int fb, int fend,
                                                const T* __restrict__ grid, T* __restrict__ four) {
   typedef typename V2T<T>::type C;
+  // the mirror of north ring j is ring nlat - 1 - j
   const RingInfo rn = gload(p.rings + ring);
-  const RingInfo rs = gload(p.rings + rn.mirror);
-  const FftClass cl = gload(p.classes + rn.cls);
-  const int32_t* rad = p.classes[rn.cls].rad;
+  const RingInfo rs = gload(p.rings + (p.nlat - 1 - ring));
+  const FftClass cl = gload(p.classes + cls);
   const C* tabs = (const C*)p.fft;
   const int h = cl.h, mmax = rn.mmax, L = cl.L;
   const int gs = cl.gshift, G = 1 << gs;
@@ -830,7 +834,7 @@ __device__ __forceinline__ void analysis_group(const DevPlan& p, int ring, int f
       }
     }
     __syncthreads();
-    dft_h<T, false, BIG>(dst, cl, rad, tabs, nullptr, lt, nt);
+    dft_h<T, false, BIG>(dst, cl, tabs, nullptr, lt, nt);
     // chirp-z classes hold y_q: Z_m = c_m conj(y_m), and
     // conj Z_{h-m} = conj(c_{h-m}) y_{h-m} with c_{h-m} = (-1)^h c_m
     const int nm = M << gs;
@@ -904,7 +908,7 @@ __global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_synthesis_kern
     if (it.ring < 0) continue;
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    synthesis_group<T, NT, BIG>(p, it.ring, it.f0, it.fend, (const T*)b.ws, (T*)b.grid, (T)b.grid_a);
+    synthesis_group<T, NT, BIG>(p, it.ring, it.cls, it.f0, it.fend, (const T*)b.ws, (T*)b.grid, (T)b.grid_a);
   }
 }
 
@@ -919,7 +923,7 @@ __global__ __launch_bounds__(NT, FftWaves<T>::value) void fourier_analysis_kerne
     if (it.ring < 0) continue;
     const DevPlan p = gload(plans + it.plan);
     const IoBind b = io ? gload(io + it.plan) : io0;
-    analysis_group<T, NT, BIG>(p, it.ring, it.f0, it.fend, (const T*)b.grid, (T*)b.ws);
+    analysis_group<T, NT, BIG>(p, it.ring, it.cls, it.f0, it.fend, (const T*)b.grid, (T*)b.ws);
   }
 }
 

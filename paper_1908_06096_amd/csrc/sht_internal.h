@@ -146,7 +146,11 @@ struct FftClass {
   int64_t post_off;   // h complex values exp(-2 pi i q / (2h))
   int64_t chirp_off;  // h complex values exp(-i pi t^2 / h)      (bluestein)
   int64_t khat_off;   // L complex: DFT_L of the conjugate chirp / L (bluestein)
+  uint64_t radpack;   // rad[0..nrad) at 6 bits each (radix q in bits 6q..6q+5), so that
+                      // the passes take their radix from a register, not a memory load
 };
+constexpr int FFT_PACK_RADICES = 10;  // radices radpack holds
+__host__ __device__ constexpr int packed_radix(uint64_t pack, int q) { return (int)((pack >> (6 * q)) & 63u); }
 
 struct MInfo {
   int32_t m;
@@ -178,6 +182,7 @@ struct FftItem {
   int32_t f0;
   int32_t plan;
   int32_t fend;
+  int32_t cls;  // the ring's FFT class (read with the ring, not after it)
 };
 
 // Device buffers of one transform: spectral [F][nspec] complex, grid
