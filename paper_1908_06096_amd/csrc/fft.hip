@@ -402,6 +402,12 @@ __device__ __noinline__ void stockham_pass(uint32_t e0, int L, int Ns,
   // sees to it): Ns = 1, no twiddles, one butterfly per thread
   constexpr bool FIRST = R > FFT_REGS;
   constexpr int MAXB = FIRST ? 1 : FFT_REGS / R;
+  // the lengths are the same on every lane; arguments arrive in vector
+  // registers, and read from the first lane the divisions below are scalar
+  L = __builtin_amdgcn_readfirstlane(L);
+  Ns = __builtin_amdgcn_readfirstlane(Ns);
+  nt = __builtin_amdgcn_readfirstlane(nt);
+  h = __builtin_amdgcn_readfirstlane(h);
   if constexpr (FIRST) Ns = 1;
   const int nb = L / R;
   // b mod Ns by multiply-high: for b < 2^14 and 1 < Ns <= 2^13,
@@ -550,6 +556,8 @@ __device__ __noinline__ void chirp_middle_pass(uint32_t e0, int L, const typenam
                                                const typename V2T<T>::type* khat, int lt, int nt) {
   typedef typename V2T<T>::type C;
   constexpr int MAXB = FFT_REGS / R;
+  L = __builtin_amdgcn_readfirstlane(L);  // uniform: a scalar division
+  nt = __builtin_amdgcn_readfirstlane(nt);
   const int nb = L / R;
   const __amdgpu_buffer_rsrc_t trs = buffer_rsrc(tw);
   const __amdgpu_buffer_rsrc_t krs = buffer_rsrc(khat);
