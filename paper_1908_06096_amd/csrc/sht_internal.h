@@ -113,6 +113,18 @@ __device__ __forceinline__ void gstore(T* p, const T& v) {
   }
 }
 
+// A store marked non-temporal (streaming): for outputs written once and not
+// read again by the kernel, so that they leave the L2 before the inputs
+// still being read.
+template <typename T>
+__device__ __forceinline__ void gstore_nt(T* p, const T& v) {
+  static_assert(sizeof(T) == 8 || sizeof(T) == 16, "8- or 16-byte values");
+  if constexpr (sizeof(T) == 8)
+    __builtin_nontemporal_store(__builtin_bit_cast(gword2, v), (SHT_GLOBAL gword2*)p);
+  else
+    __builtin_nontemporal_store(__builtin_bit_cast(gword4, v), (SHT_GLOBAL gword4*)p);
+}
+
 // ---------------------------------------------------------------------------
 // Device metadata
 // ---------------------------------------------------------------------------
