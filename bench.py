@@ -552,6 +552,7 @@ def run_small_configs(steps):
     r = run_gpu("T399-full-400x800-F411", "fp64", steps, 1)
     geo = geometry_counts(r["N"], r["grid"])
     st, rf = stage_report(r["N"], geo, r["F"], "fp64", r["per_stage_ms"])
+    rf["traffic"] = committed_traffic("T399-full-400x800-F411", "fp64", rf["kernel"])
     out["T399-full-400x800-F411"] = {"precision": "fp64", "steps": steps,
                                      "ms_per_step": r["total_ms"] / steps,
                                      "value": 2.0 * r["F"] * steps / (r["total_ms"] * 1e-3),
@@ -666,6 +667,7 @@ def main():
         torch.cuda.empty_cache()
         r = run_gpu(args.workload, prec, args.steps, 1)
         st, rf = stage_report(N, geo, F, prec, r["per_stage_ms"])
+        rf["traffic"] = committed_traffic(args.workload, prec, rf["kernel"])
         variants[prec] = {
             "value": 2.0 * F * r["steps"] / (r["total_ms"] * 1e-3),
             "ms_per_step": r["total_ms"] / r["steps"],
