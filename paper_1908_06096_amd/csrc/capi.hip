@@ -5,6 +5,7 @@
 // or copies metadata happens once at plan (or batch) creation; the transform
 // calls only enqueue kernels.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -496,6 +497,59 @@ bool fourier_offsets_fit(const sht_plan_s* p) {
   return 2 * ((int64_t)mm + 1) * p->Fp * csize < ((int64_t)1 << 31);
 }
 
+// The FFT classes of the distinct half lengths hs (sorted) of a grid with
+// npts points: transform length and radix plan, table offsets, tier, fields
+// per work group and packed radices; *fft_bytes receives the size of their
+// tables.
+int make_fft_classes(int prec, int64_t npts, const std::vector<int>& hs, std::vector<FftClass>* classes,
+                     size_t* fft_bytes) {
+  const int csize = (prec == SHT_FP64) ? 16 : 8;
+  classes->clear();
+  int64_t off = 0;
+  for (int h : hs) {
+    FftClass c{};
+    c.h = h;
+    if (radix_smooth(h, prec) && !radices(h).empty()) {
+      c.L = h;
+      c.bluestein = 0;
+    } else {
+      c.L = bluestein_length(h);
+      c.bluestein = 1;
+    }
+    std::vector<int> rad = c.L > 0 ? radices(c.L, FFT_THREADS, c.bluestein) : std::vector<int>();
+    // a chirp-z transform fuses its middle passes, which takes two passes
+    if (rad.empty() || (int)rad.size() > FFT_MAX_RADICES || (c.bluestein && rad.size() < 2)) return SHT_EUNSUPPORTED;
+    c.nrad = (int)rad.size();
+    for (size_t q = 0; q < rad.size(); ++q) c.rad[q] = rad[q];
+    c.root_off = off;
+    off += c.L;
+    c.post_off = off;
+    off += h;
+    if (c.bluestein) {
+      c.chirp_off = off;
+      off += h;
+      c.khat_off = off;
+      off += c.L;
+    }
+    classes->push_back(c);
+  }
+  *fft_bytes = (size_t)off * csize;
+  choose_groups(prec, npts, classes);
+  for (FftClass& c : *classes) {
+    if (c.nrad > FFT_PACK_RADICES) return SHT_EUNSUPPORTED;
+    c.radpack = 0;
+    for (int q = 0; q < c.nrad; ++q) c.radpack |= (uint64_t)c.rad[q] << (6 * q);
+  }
+  return SHT_OK;
+}
+
+// Class lists by (device, grid, truncation, precision), kept for the life of
+// the process: the chirp-z length search, the radix plans and the group
+// choice take ~16 ms of host time at TCo1279, and a served truncation's
+// tables are made again after every eviction.
+std::mutex g_cls_mu;
+std::map<std::array<int, 4>, std::pair<std::vector<FftClass>, size_t>> g_cls_cache;
+
 int build_host(sht_plan_s* p) {
   const int N = p->N;
   // ---- geometry ----
@@ -532,45 +586,31 @@ int build_host(sht_plan_s* p) {
   if (!fourier_offsets_fit(p)) return SHT_EUNSUPPORTED;
 
   // ---- FFT classes (one per distinct half length) ----
-  const int csize = (p->prec == SHT_FP64) ? 16 : 8;
   std::vector<int> hs;
   for (auto& r : p->rings) hs.push_back(r.nlon / 2);
   std::sort(hs.begin(), hs.end());
   hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
-  int64_t off = 0;
-  for (int h : hs) {
-    FftClass c{};
-    c.h = h;
-    if (radix_smooth(h, p->prec) && !radices(h).empty()) {
-      c.L = h;
-      c.bluestein = 0;
-    } else {
-      c.L = bluestein_length(h);
-      c.bluestein = 1;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    // bf16x3 plans transform in FP32: the same classes as FP32 plans
+    const std::array<int, 4> key{dev, p->grid, N, p->prec == SHT_FP64 ? SHT_FP64 : SHT_FP32};
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> lk(g_cls_mu);
+      auto it = g_cls_cache.find(key);
+      if (it != g_cls_cache.end()) {
+        p->classes = it->second.first;
+        p->fft_bytes = it->second.second;
+        hit = true;
+      }
     }
-    std::vector<int> rad = c.L > 0 ? radices(c.L, FFT_THREADS, c.bluestein) : std::vector<int>();
-    // a chirp-z transform fuses its middle passes, which takes two passes
-    if (rad.empty() || (int)rad.size() > FFT_MAX_RADICES || (c.bluestein && rad.size() < 2)) return SHT_EUNSUPPORTED;
-    c.nrad = (int)rad.size();
-    for (size_t q = 0; q < rad.size(); ++q) c.rad[q] = rad[q];
-    c.root_off = off;
-    off += c.L;
-    c.post_off = off;
-    off += h;
-    if (c.bluestein) {
-      c.chirp_off = off;
-      off += h;
-      c.khat_off = off;
-      off += c.L;
+    if (!hit) {
+      const int rc = make_fft_classes(p->prec, p->npts, hs, &p->classes, &p->fft_bytes);
+      if (rc != SHT_OK) return rc;
+      std::lock_guard<std::mutex> lk(g_cls_mu);
+      g_cls_cache.emplace(key, std::make_pair(p->classes, p->fft_bytes));
     }
-    p->classes.push_back(c);
-  }
-  p->fft_bytes = (size_t)off * csize;
-  choose_groups(p->prec, p->npts, &p->classes);
-  for (FftClass& c : p->classes) {
-    if (c.nrad > FFT_PACK_RADICES) return SHT_EUNSUPPORTED;
-    c.radpack = 0;
-    for (int q = 0; q < c.nrad; ++q) c.radpack |= (uint64_t)c.rad[q] << (6 * q);
   }
   for (auto& r : p->rings) {
     const int h = r.nlon / 2;
