@@ -273,6 +273,15 @@ void legendre_items_raw(const sht_plan_s* p, int variant, int plan, std::vector<
   int ir, ic, dr, dc;
   legendre_tiles(p->prec, variant, &ir, &ic, &dr, &dc);
   const int twoF = 2 * p->F;
+  const size_t ncol_i = (size_t)(twoF + ic - 1) / ic, ncol_d = (size_t)(twoF + dc - 1) / dc;
+  size_t ni = 0, nd = 0;
+  for (const MInfo& mi : p->ms) {
+    if (mi.L == 0) continue;
+    ni += (size_t)(mi.L + ir - 1) / ir * ncol_i;
+    nd += (size_t)(std::max(mi.K[0], mi.K[1]) + dr - 1) / dr * ncol_d;
+  }
+  inv->reserve(inv->size() + ni);
+  dir->reserve(dir->size() + nd);
   for (const MInfo& mi : p->ms) {
     if (mi.L == 0) continue;
     for (int t0 = 0; t0 < mi.L; t0 += ir)
@@ -300,6 +309,7 @@ void legendre_arrange(std::vector<WorkItem>* items, Steps steps) {
   std::vector<WorkItem> in;
   in.swap(*items);
   std::vector<WorkItem> q[NUM_XCD];
+  for (auto& v : q) v.reserve(in.size() / NUM_XCD + 64);
   double load[NUM_XCD] = {0};
   size_t i = 0;
   while (i < in.size()) {
@@ -312,6 +322,7 @@ void legendre_arrange(std::vector<WorkItem>* items, Steps steps) {
   }
   size_t most = 0;
   for (const auto& v : q) most = std::max(most, v.size());
+  items->reserve(most * NUM_XCD);
   for (size_t r = 0; r < most; ++r)
     for (int x = 0; x < NUM_XCD; ++x) items->push_back(r < q[x].size() ? q[x][r] : WorkItem{-1, 0, 0, 0});
 }
@@ -373,26 +384,34 @@ void fft_items(const sht_plan_s* p, int plan, std::vector<FftItem>* syn, std::ve
 // side by side (empty slots where a chunk has fewer groups than the others
 // of its eight): they run on one XCD at the same time, and their strided
 // reads and writes of the chunk's Fourier rows (fields are the innermost
-// index) meet in that XCD's L2.
-void fft_arrange(const sht_plan_t* plans, std::vector<FftItem>* items) {
-  std::vector<FftItem> chunks;
-  chunks.swap(*items);
+// index) meet in that XCD's L2.  The groups are appended to *items.
+void fft_arrange(const sht_plan_t* plans, const std::vector<FftItem>& chunks, std::vector<FftItem>* items) {
+  // work groups per chunk, and the list's length (8 chunks side by side,
+  // each group of them as long as its longest)
+  std::vector<int> ng(chunks.size());
+  size_t total = 0;
   for (size_t c0 = 0; c0 < chunks.size(); c0 += NUM_XCD) {
-    const int nc = (int)std::min<size_t>(NUM_XCD, chunks.size() - c0);
-    int G[NUM_XCD], ng[NUM_XCD], most = 0;
-    for (int k = 0; k < nc; ++k) {
-      const FftItem& c = chunks[c0 + k];
-      const sht_plan_s* p = plans[c.plan];
-      G[k] = p->classes[p->rings[c.ring].cls].G;
-      ng[k] = (c.fend - c.f0 + G[k] - 1) / G[k];
+    int most = 0;
+    for (size_t k = c0; k < std::min(chunks.size(), c0 + NUM_XCD); ++k) {
+      const FftItem& c = chunks[k];
+      const int G = plans[c.plan]->classes[c.cls].G;
+      ng[k] = (c.fend - c.f0 + G - 1) / G;
       most = std::max(most, ng[k]);
     }
+    total += (size_t)most * NUM_XCD;
+  }
+  items->reserve(items->size() + total);
+  for (size_t c0 = 0; c0 < chunks.size(); c0 += NUM_XCD) {
+    const int nc = (int)std::min<size_t>(NUM_XCD, chunks.size() - c0);
+    int most = 0;
+    for (int k = 0; k < nc; ++k) most = std::max(most, ng[c0 + k]);
     for (int j = 0; j < most; ++j)
       for (int k = 0; k < NUM_XCD; ++k) {
-        if (k < nc && j < ng[k]) {
+        if (k < nc && j < ng[c0 + k]) {
           const FftItem& c = chunks[c0 + k];
-          const int f0 = c.f0 + j * G[k];
-          items->push_back(FftItem{c.ring, f0, c.plan, std::min(f0 + G[k], c.fend), c.cls});
+          const int G = plans[c.plan]->classes[c.cls].G;
+          const int f0 = c.f0 + j * G;
+          items->push_back(FftItem{c.ring, f0, c.plan, std::min(f0 + G, c.fend), c.cls});
         } else {
           items->push_back(FftItem{-1, 0, 0, 0, 0});
         }
@@ -481,9 +500,8 @@ hipError_t fft_launch_tiers(bool synthesis, const DevPlan* plans, int prec, cons
 void fft_join(const sht_plan_t* plans, std::vector<FftItem>* tiers, std::vector<FftItem>* out, int* off) {
   out->clear();
   for (int t = 0; t < FFT_TIERS; ++t) {
-    fft_arrange(plans, &tiers[t]);
     off[t] = (int)out->size();
-    out->insert(out->end(), tiers[t].begin(), tiers[t].end());
+    fft_arrange(plans, tiers[t], out);
   }
   off[FFT_TIERS] = (int)out->size();
 }
