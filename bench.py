@@ -317,7 +317,7 @@ def run_batch(steps, warmup, precision="fp32"):
     return out
 
 
-def run_serving(n_requests=1000, slots=4, budget_gb=40.0, load=0.8, bypass=0):
+def run_serving(n_requests=1000, slots=4, budget_gb=40.0, load=0.8, bypass=2):
     """Serving stream: Poisson arrivals of round-trip requests, truncation
     log-uniform over T79-T1279 snapped to a ladder of resident resolutions,
     1-411 fields, FP32 or bf16x3 with probability 1/2 each.  The arrival rate
@@ -328,7 +328,8 @@ def run_serving(n_requests=1000, slots=4, budget_gb=40.0, load=0.8, bypass=0):
     22 GB), so admission waits for memory and idle table sets are evicted
     (and made again when a request needs them; that time is in its latency).
     Up to `bypass` later requests that fit may start ahead of one that waits
-    for memory (0: strict arrival order, which measured the lower p99)."""
+    for memory (0: strict arrival order; 1 to 4 measured a p99 ~10 ms lower
+    than 0 at the 40 GB budget)."""
     import torch
 
     from paper_1908_06096_amd.serve import TRUNCATION_LADDER, GpuExecutor, Scheduler, draw_requests, percentile

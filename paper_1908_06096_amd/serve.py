@@ -380,3 +380,9 @@ class GpuExecutor:
         self.tables.clear()
         self.pools.clear()
         self.pool_bytes = 0
+        # the requests' buffers came from torch's caching allocator, which
+        # keeps freed blocks for torch alone: hand them back to the device,
+        # where the library's tables and the kernels' scratch memory are
+        # allocated (a later run could otherwise find the device full)
+        self.torch.cuda.synchronize()
+        self.torch.cuda.empty_cache()
