@@ -44,20 +44,20 @@ bool five_smooth(int64_t x) {
 }
 
 // A length the passes of a precision can factor: no prime factor above its
-// largest prime radix, 47 in FP32 (the primes above FFT_BIG_PRIME run in
-// kernels of their own) and FFT_BIG_PRIME in FP64 (where those butterflies
-// spill).
+// largest prime radix, FFT_MAX_PRIME in FP32 (the primes above FFT_BIG_PRIME
+// run in kernels of their own) and FFT_BIG_PRIME in FP64 (where those
+// butterflies spill).
 bool radix_smooth(int64_t x, int prec) {
   if (x < 1) return false;
-  const int maxp = prec == SHT_FP64 ? FFT_BIG_PRIME : 47;
-  for (int p : {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47})
+  const int maxp = prec == SHT_FP64 ? FFT_BIG_PRIME : FFT_MAX_PRIME;
+  for (int p : {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37})
     if (p <= maxp)
       while (x % p == 0) x /= p;
   return x == 1;
 }
 
 // Radices the passes can use (each has a register butterfly), larger first.
-constexpr int kRadices[] = {47, 43, 41, 37, 31, 29, 23, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
+constexpr int kRadices[] = {37, 31, 29, 23, 20, 19, 18, 17, 16, 15, 14, 13, 12, 11, 10, 9, 8, 7, 6, 5, 4, 3, 2};
 
 // A pass of radix R over L points fits `threads` threads when its L / R
 // butterflies fit the FFT_REGS / R butterflies each thread holds (one for
@@ -85,7 +85,7 @@ int fewest_passes(int L, int x, int threads, std::map<int, std::pair<int, int>>*
   return bp;
 }
 
-// Radix sequence for a length without prime factors above 47 (the chirp-z
+// Radix sequence for a length without prime factors above FFT_MAX_PRIME (the chirp-z
 // lengths are 5-smooth): the fewest passes that all fit
 // `threads` threads, the larger radix first among equally short sequences.
 // Each pass is one LDS round trip and two barriers, which is what the

@@ -5,7 +5,7 @@
 // A ring of n = 2h points is transformed as a complex DFT of length h of
 // z_t = g_{2t} + i g_{2t+1} plus an O(h) pre/post step.  The complex DFT is
 // an in-LDS Stockham autosort FFT when h has no prime factor above the
-// largest prime radix (47 in FP32, 23 in FP64); otherwise it is the chirp-z (Bluestein) identity
+// largest prime radix (37 in FP32, 23 in FP64); otherwise it is the chirp-z (Bluestein) identity
 //   X_q = c_q sum_t (z_t c_t) conj(c_{q-t}),  c_t = exp(-i pi t^2 / h),
 // evaluated as a cyclic convolution of 5-smooth length L >= 2h - 1 with two
 // more FFTs.  Inverse DFTs use conj(DFT(conj(x))).
@@ -252,13 +252,12 @@ __device__ inline void butterfly_odd(typename V2T<T>::type* v) {
 }
 
 __host__ __device__ constexpr bool odd_prime_radix(int R) {
-  return R == 7 || R == 11 || R == 13 || R == 17 || R == 19 || R == 23 || R == 29 || R == 31 || R == 37 ||
-         R == 41 || R == 43 || R == 47;
+  return R == 7 || R == 11 || R == 13 || R == 17 || R == 19 || R == 23 || R == 29 || R == 31 || R == 37;
 }
 
 // Forward DFT of R points in registers.  Radices 2, 3, 4 and 5 are written
 // out; 8 and 16 take one even/odd step, 9 a 3 x 3 step, the odd primes
-// from 7 to 47 the pair form above, and the composite radices 6, 10, 12,
+// from 7 to 37 the pair form above, and the composite radices 6, 10, 12,
 // 14, 15, 18 and 20 the generic step above.
 template <typename T, int R>
 __device__ inline void butterfly(typename V2T<T>::type* v) {
@@ -487,9 +486,6 @@ __device__ __forceinline__ void pass_dispatch(int R, uint32_t e0, int L, int Ns,
   constexpr bool PLAIN_LEN = MODE == OUT_PLAIN || MODE == OUT_GRID || MODE == OUT_GRID_LOG;
   if constexpr (PLAIN_LEN && BIG && sizeof(T) == 4) {
     switch (R) {
-      case 47: SHT_PASS(47); return;
-      case 43: SHT_PASS(43); return;
-      case 41: SHT_PASS(41); return;
       case 37: SHT_PASS(37); return;
       case 31: SHT_PASS(31); return;
       case 29: SHT_PASS(29); return;

@@ -41,6 +41,11 @@ constexpr int FFT_THREADS = 512;
 constexpr int FFT_THREADS_SMALL = 256;
 constexpr int FFT_TIERS = 4;
 constexpr int FFT_BIG_PRIME = 23;
+// The largest prime radix in FP32.  41, 43 and 47 were radices too, but their
+// passes saved and reloaded ~48 callee-saved registers per call and spilled
+// (their rings moved ~4.7x their algorithmic bytes); as chirp-z classes the
+// stages measured the same or faster.
+constexpr int FFT_MAX_PRIME = 37;
 __host__ __device__ constexpr int fft_tier_threads(int tier) { return (tier & 1) ? FFT_THREADS : FFT_THREADS_SMALL; }
 constexpr int FFT_REGS = 20;
 constexpr int FFT_MAX_RADICES = 20;
@@ -144,7 +149,7 @@ struct RingInfo {
 
 // One FFT class per distinct half length h = nlon / 2.  The real DFT of
 // length 2h is carried out as a complex DFT of length h; when h has a prime
-// factor above the largest prime radix (47 in FP32, 23 in FP64) that DFT is
+// factor above the largest prime radix (37 in FP32, 23 in FP64) that DFT is
 // a chirp-z convolution of length L (5-smooth, L >= 2h - 1), otherwise
 // L = h.
 struct FftClass {

@@ -1,10 +1,10 @@
 """Ring-length coverage of the FFT stages: full grids whose single ring
 length 2h (h = N + 1) takes each prime radix of the passes (7, 11, 13, 17,
-19 and 23; in FP32 also 29 to 47, in kernels of their own; primes above 20
-as a first pass only), the composite radix 14, or the chirp-z convolution
-with a short length (FP64 above 23, both precisions above 47), compared with
-the oracle in both directions and round-tripped; two fields, so that work
-groups holding several fields run partly empty."""
+19 and 23; in FP32 also 29, 31 and 37, in kernels of their own; primes
+above 20 as a first pass only), the composite radix 14, or the chirp-z
+convolution with a short length (FP64 above 23, both precisions above 37),
+compared with the oracle in both directions and round-tripped; two fields,
+so that work groups holding several fields run partly empty."""
 
 import numpy as np
 import pytest
@@ -26,7 +26,8 @@ TRUNCATIONS = [
     97,   # h = 98 = 2 * 7 * 7
     181,  # h = 182 = 2 * 7 * 13
     57,   # h = 58 = 2 * 29: radix 29 (FP32), chirp-z (FP64)
-    93,   # h = 94 = 2 * 47: radix 47 (FP32), chirp-z (FP64)
+    61,   # h = 62 = 2 * 31: radix 31 (FP32), chirp-z (FP64)
+    93,   # h = 94 = 2 * 47: chirp-z (both)
     221,  # h = 222 = 2 * 3 * 37: radix 37 and two more passes (FP32)
     105,  # h = 106 = 2 * 53: chirp-z
     201,  # h = 202 = 2 * 101: chirp-z
